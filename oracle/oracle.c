@@ -1,0 +1,226 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for exact locally
+ * adaptive binarization (Mollah, Basu, Nasipuri, "Computationally Efficient
+ * Implementation of Convolution-based Locally Adaptive Binarization
+ * Techniques", arXiv:1210.3165).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * with the HIP library.
+ *
+ * What it computes, per pixel (x, y), straight from the definitions:
+ *   - gray level f (Sec. 1, Eq. 1): f = w_r r + w_g g + w_b b with the
+ *     weights 0.299 / 0.587 / 0.114, evaluated exactly in integers as
+ *     (299 r + 587 g + 114 b) / 1000 and rounded half up;
+ *   - the W x W window S around the pixel (Sec. 2), clipped to the image;
+ *     n = number of in-image window pixels;
+ *   - S1 = sum of f over S, S2 = sum of f^2 over S (exact integers);
+ *   - mean m = S1 / n and standard deviation s = sqrt(sum (f - m)^2 / n)
+ *     (Sec. 1, the quantities of Eq. 4), taken as the population deviation,
+ *     second pass over the window, in double precision;
+ *   - threshold t (double): Sauvola, Eq. 4: t = m [1 + k (s / R - 1)];
+ *     Niblack: t = m + k s;
+ *   - binary output (Sec. 1, Eq. 3): g = 0 if f < t, 255 otherwise.
+ *
+ * Window placement: rows [y - lo, y + hi], columns [x - lo, x + hi] with
+ * lo = floor(win / 2), hi = win - 1 - lo, intersected with the image.
+ *
+ * Parity pins: every function here is checked by the CPU test suite against
+ * brute force on tiny images, a summed-area table, closed forms and library
+ * statistics; none of those checks reuses this code.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_RANGE (-2)
+#define OR_ERR_NOMEM (-3)
+
+int oracle_version(void) { return 1; }
+
+/* Sec. 1, Eq. 1: gray level of one pixel. */
+static uint8_t gray_pixel(const uint8_t *px, int channels) {
+    if (channels == 1) return px[0];
+    uint32_t num = 299u * px[0] + 587u * px[1] + 114u * px[2];
+    /* round half up: floor(num / 1000 + 1/2) */
+    return (uint8_t)((num + 500u) / 1000u);
+}
+
+/* Sec. 1, Eq. 1 over a whole image (H x W, interleaved channels). */
+int oracle_gray(const uint8_t *img, int64_t H, int64_t W, int channels,
+                uint8_t *gray) {
+    if (!img || !gray || H < 0 || W < 0) return OR_ERR_ARG;
+    if (channels != 1 && channels != 3) return OR_ERR_ARG;
+    int64_t npx = H * W;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npx; ++i)
+        gray[i] = gray_pixel(img + i * channels, channels);
+    return OR_OK;
+}
+
+/* Everything the method determines for one pixel. */
+typedef struct {
+    uint32_t s1, s2, n;
+    double m, s, t;
+    uint8_t g;
+} px_result;
+
+/* Window statistics, threshold and decision for pixel (x, y) of the gray
+ * image f (H x W).  rule 0 = Sauvola (Eq. 4), rule 1 = Niblack. */
+static int pixel(const uint8_t *f, int H, int W, int win, double k, double R,
+                 int rule, int y, int x, px_result *res) {
+    int lo = win / 2, hi = win - 1 - lo;
+    int ya = y - lo < 0 ? 0 : y - lo;
+    int yb = y + hi > H - 1 ? H - 1 : y + hi;
+    int xa = x - lo < 0 ? 0 : x - lo;
+    int xb = x + hi > W - 1 ? W - 1 : x + hi;
+
+    /* first pass over S: sums of f and f^2 */
+    uint64_t a = 0, b = 0;
+    for (int yy = ya; yy <= yb; ++yy)
+        for (int xx = xa; xx <= xb; ++xx) {
+            uint64_t v = f[(size_t)yy * W + xx];
+            a += v;
+            b += v * v;
+        }
+    uint64_t n = (uint64_t)(yb - ya + 1) * (uint64_t)(xb - xa + 1);
+    if (a > 0xFFFFFFFFull || b > 0xFFFFFFFFull) return OR_ERR_RANGE;
+
+    double m = (double)a / (double)n;
+
+    /* second pass over S: population variance about the mean */
+    double acc = 0.0;
+    for (int yy = ya; yy <= yb; ++yy)
+        for (int xx = xa; xx <= xb; ++xx) {
+            double d = (double)f[(size_t)yy * W + xx] - m;
+            acc += d * d;
+        }
+    double s = sqrt(acc / (double)n);
+
+    double t;
+    if (rule == 0)
+        t = m * (1.0 + k * (s / R - 1.0)); /* Eq. 4 */
+    else
+        t = m + k * s; /* Niblack */
+
+    res->s1 = (uint32_t)a;
+    res->s2 = (uint32_t)b;
+    res->n = (uint32_t)n;
+    res->m = m;
+    res->s = s;
+    res->t = t;
+    res->g = ((double)f[(size_t)y * W + x] < t) ? 0 : 255; /* Eq. 3 */
+    return OR_OK;
+}
+
+static int check_args(const uint8_t *img, int H, int W, int channels, int win,
+                      double R, int rule) {
+    if (!img || H < 1 || W < 1) return OR_ERR_ARG;
+    if (channels != 1 && channels != 3) return OR_ERR_ARG;
+    if (win < 1 || win > 255) return OR_ERR_ARG;
+    if (rule != 0 && rule != 1) return OR_ERR_ARG;
+    if (rule == 0 && !(R > 0.0)) return OR_ERR_ARG;
+    return OR_OK;
+}
+
+/*
+ * Whole-image reference.  Every output pointer may be NULL except `out`.
+ * gray: H*W u8; s1, s2, n: H*W u32; m, s, t: H*W f64; out: H*W u8.
+ */
+int oracle_binarize(const uint8_t *img, int H, int W, int channels, int win,
+                    double k, double R, int rule, uint8_t *gray, uint32_t *s1,
+                    uint32_t *s2, uint32_t *n, double *m, double *s, double *t,
+                    uint8_t *out) {
+    int rc = check_args(img, H, W, channels, win, R, rule);
+    if (rc) return rc;
+    if (!out) return OR_ERR_ARG;
+    size_t npx = (size_t)H * (size_t)W;
+    uint8_t *f = gray ? gray : (uint8_t *)malloc(npx);
+    if (!f) return OR_ERR_NOMEM;
+    oracle_gray(img, H, W, channels, f);
+
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            px_result r;
+            if (pixel(f, H, W, win, k, R, rule, y, x, &r)) {
+                bad = 1;
+                continue;
+            }
+            size_t i = (size_t)y * W + x;
+            if (s1) s1[i] = r.s1;
+            if (s2) s2[i] = r.s2;
+            if (n) n[i] = r.n;
+            if (m) m[i] = r.m;
+            if (s) s[i] = r.s;
+            if (t) t[i] = r.t;
+            out[i] = r.g;
+        }
+    }
+    if (!gray) free(f);
+    return bad ? OR_ERR_RANGE : OR_OK;
+}
+
+/*
+ * Sampled reference: the same quantities at npts chosen pixels (ys[i], xs[i])
+ * of a large image, so that full-size launches can be checked point by point.
+ * Every output array has npts entries; any may be NULL except out.
+ */
+int oracle_binarize_points(const uint8_t *img, int H, int W, int channels,
+                           int win, double k, double R, int rule,
+                           const int32_t *ys, const int32_t *xs, int64_t npts,
+                           uint8_t *fval, uint32_t *s1, uint32_t *s2,
+                           uint32_t *n, double *m, double *s, double *t,
+                           uint8_t *out) {
+    int rc = check_args(img, H, W, channels, win, R, rule);
+    if (rc) return rc;
+    if (!ys || !xs || !out || npts < 0) return OR_ERR_ARG;
+    for (int64_t i = 0; i < npts; ++i)
+        if (ys[i] < 0 || ys[i] >= H || xs[i] < 0 || xs[i] >= W) return OR_ERR_ARG;
+
+    size_t npx = (size_t)H * (size_t)W;
+    uint8_t *f = (uint8_t *)malloc(npx);
+    if (!f) return OR_ERR_NOMEM;
+    oracle_gray(img, H, W, channels, f);
+
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t i = 0; i < npts; ++i) {
+        px_result r;
+        if (pixel(f, H, W, win, k, R, rule, ys[i], xs[i], &r)) {
+            bad = 1;
+            continue;
+        }
+        if (fval) fval[i] = f[(size_t)ys[i] * W + xs[i]];
+        if (s1) s1[i] = r.s1;
+        if (s2) s2[i] = r.s2;
+        if (n) n[i] = r.n;
+        if (m) m[i] = r.m;
+        if (s) s[i] = r.s;
+        if (t) t[i] = r.t;
+        out[i] = r.g;
+    }
+    free(f);
+    return bad ? OR_ERR_RANGE : OR_OK;
+}
+
+/* Number of OpenMP threads the oracle runs with (for reporting). */
+int oracle_num_threads(void) {
+    int nt = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            nt = omp_get_num_threads();
+#endif
+        }
+    }
+    return nt;
+}
