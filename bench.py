@@ -1,0 +1,244 @@
+"""Benchmark of exact Sauvola / Niblack binarization on one MI355X.
+
+Default workload: the 4096 x 4096 gray synthetic page, binarized with Sauvola
+(k 0.5, R 128) at windows 15, 31, 61 and 101 and with Niblack (k -0.2) at
+window 31.  One step = those five binarizations, each on its own input/output
+buffer pair from a rotating pool larger than the 256 MB Infinity Cache, so the
+bytes come from HBM.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0):
+  value      Gpixel/s over the timed steps (pixels binarized / time)
+  roofline   achieved algorithmic HBM GB/s of the dominant kernel (Sauvola,
+             gray, 256-column tiles: 2 bytes per pixel) from HIP events
+             around each of its launches, against the 8 TB/s MI355X peak
+  cpu_baseline  the CPU oracle timed on this host on a bounded pixel sample
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpixel/s + % HBM peak, Sauvola W=15–101; served p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+CASES = [  # (rule, win, k) of the 4096^2 workload
+    (0, 15, 0.5), (0, 31, 0.5), (0, 61, 0.5), (0, 101, 0.5), (1, 31, -0.2),
+]
+RULE_NAME = {0: "sauvola", 1: "niblack"}
+DOMINANT = "bz_page_kernel<256, gray, sauvola>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bz_page_kernel_sauvola_gray_4096.json")
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1210_3165_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _f32(x: float) -> float:
+    return float(np.float32(x))
+
+
+def run_cpu_baseline(img: np.ndarray, budget_s: float) -> dict:
+    """The oracle (unchanged, all host threads) on a random pixel sample of
+    the same five cases, scaled to Gpixel/s."""
+    import oracle
+    oracle.build(force=False)
+    H, W = img.shape[:2]
+    rng = np.random.default_rng(12345)
+    def timed(n):
+        ys = rng.integers(0, H, n).astype(np.int32)
+        xs = rng.integers(0, W, n).astype(np.int32)
+        t0 = time.perf_counter()
+        for rule, win, k in CASES:
+            oracle.binarize_points(img, win, _f32(k), 128.0, rule, ys, xs)
+        return time.perf_counter() - t0
+
+    # grow a probe sample until it takes a measurable time, then size the
+    # final sample to the budget
+    n = 256
+    while n < 2_000_000:
+        dt = timed(n)
+        if dt > 0.1 * budget_s:
+            break
+        n *= 4
+    n = int(min(2_000_000, max(256, n * budget_s / max(dt, 1e-6))))
+    ys = rng.integers(0, H, n).astype(np.int32)
+    xs = rng.integers(0, W, n).astype(np.int32)
+    t0 = time.perf_counter()
+    for rule, win, k in CASES:
+        oracle.binarize_points(img, win, _f32(k), 128.0, rule, ys, xs)
+    dt = time.perf_counter() - t0
+    px = n * len(CASES)
+    return {
+        "value": px / dt / 1e9,
+        "unit": "Gpixel/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} random pixels of the 4096x4096 page for each of the 5 cases "
+                  f"({px} window evaluations, {dt:.1f} s); direct window loop, fp64",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--pool-mb", type=int, default=1024, help="rotating buffer pool size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--size", type=int, default=4096)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(pages are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import pagegen
+    import paper_1210_3165_amd as bz
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bz.lib()
+
+    S = args.size
+    page = pagegen.config1(size=S)[0].img
+    px = S * S
+    pair_bytes = 2 * px
+    n_pairs = max(2, math.ceil(args.pool_mb * 2**20 / pair_bytes))
+    src = torch.from_numpy(page).to(dev)
+    ins = [src.clone() for _ in range(n_pairs)]
+    outs = [torch.empty((S, S), dtype=torch.uint8, device=dev) for _ in range(n_pairs)]
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    idx = 0
+
+    def launch(case):
+        nonlocal idx
+        rule, win, k = case
+        b = idx % n_pairs
+        idx += 1
+        bz.binarize(ins[b], win, k, 128.0, rule, out=outs[b])
+
+    for _ in range(args.warmup):
+        for c in CASES:
+            launch(c)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, an event between consecutive launches
+    nl = args.steps * len(CASES)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    t_wall = time.perf_counter()
+    for s in range(args.steps):
+        for i, c in enumerate(CASES):
+            launch(c)
+            ev[s * len(CASES) + i + 1].record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = ev[0].elapsed_time(ev[nl])
+    per = np.array([ev[j].elapsed_time(ev[j + 1]) for j in range(nl)]).reshape(args.steps, len(CASES))
+
+    cases = []
+    for i, (rule, win, k) in enumerate(CASES):
+        ms = float(np.mean(per[:, i]))
+        cases.append({"rule": RULE_NAME[rule], "win": win, "k": k, "ms": ms,
+                      "gpix_s": px / (ms * 1e-3) / 1e9,
+                      "hbm_frac": 2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS})
+    # dominant kernel: the Sauvola gray launches (4 of the 5 per step)
+    sauv = per[:, [i for i, c in enumerate(CASES) if c[0] == 0]]
+    avg_ms = float(np.mean(sauv))
+    achieved = 2 * px / (avg_ms * 1e-3) / 1e9
+
+    # achievable copy bandwidth over the same pool (plain copy kernel)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 4 * n_pairs
+    e0.record(stream)
+    for r in range(reps):
+        outs[r % n_pairs].copy_(ins[(r + 1) % n_pairs])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 2 * px * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    traffic = measured_traffic()
+    step_ms = total_ms / args.steps
+    rec = {
+        "metric": METRIC,
+        "value": px * len(CASES) / (step_ms * 1e-3) / 1e9,
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{S}x{S} u8 gray synthetic page; one step = Sauvola k=0.5 R=128 at "
+                        "win 15, 31, 61, 101 + Niblack k=-0.2 at win 31",
+            "H": S, "W": S, "channels": 1,
+            "tiles": {str(w): list(bz.default_tile(S, S, 1, w)) for _, w, _ in CASES},
+            "pool_pairs": n_pairs,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "kernel": DOMINANT,
+            "bytes_per_launch": 2 * px,
+            "avg_launch_ms": avg_ms,
+        },
+        "cases": cases,
+        "copy_GBps": copy_gbps,
+        "wall_s": t_wall,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = run_cpu_baseline(page, args.cpu_budget)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

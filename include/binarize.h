@@ -1,0 +1,130 @@
+/*
+ * binarize.h -- C ABI of libbinarize.so: exact locally adaptive (Sauvola /
+ * Niblack) binarization of 8-bit document images on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Mollah, Basu, Nasipuri, "Computationally Efficient Implementation
+ * of Convolution-based Locally Adaptive Binarization Techniques",
+ * arXiv:1210.3165.  For every pixel the library computes the mean m and the
+ * standard deviation s of the gray levels in the W x W window around it
+ * (Sec. 2), the Sauvola threshold t = m [1 + k (s / R - 1)] (Sec. 1, Eq. 4) or
+ * the Niblack threshold t = m + k s, and the binary output g = 0 if f < t,
+ * 255 otherwise (Sec. 1, Eq. 3).  Colour input is first reduced to gray with
+ * the weights 0.299 / 0.587 / 0.114 (Sec. 1, Eq. 1).  The window statistics are
+ * exact (full window, not the paper's sampled subset S').
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Image layout  img: H rows x W_img columns x `channels` bytes, row-major,
+ *               rows contiguous (row pitch = W_img * channels), channels
+ *               interleaved r, g, b.  out: H x W_img bytes, row pitch W_img.
+ * Gray level    channels == 1: f = img.  channels == 3:
+ *               f = (299 r + 587 g + 114 b + 500) / 1000 in integers, i.e. the
+ *               Eq. 1 weighted sum rounded to nearest with halves up.
+ * Window        rows [y - lo, y + hi] and columns [x - lo, x + hi] with
+ *               lo = win / 2 and hi = win - 1 - lo (an even window reaches one
+ *               further up/left), intersected with the image; n is the number
+ *               of in-image window pixels.  Window sums S1 = sum f and
+ *               S2 = sum f^2 are exact 32-bit integers for win <= 255.
+ * Statistics    m = S1 / n, s = sqrt(n S2 - S1^2) / n (population deviation;
+ *               n S2 - S1^2 is formed exactly).
+ * Threshold     rule BZ_SAUVOLA: t = m (1 + k (s / R - 1))   (Eq. 4)
+ *               rule BZ_NIBLACK: t = m + k s                 (R unused)
+ *               evaluated in fp32 from the exact integer sums; |t - t_exact|
+ *               stays below 1e-4 gray levels.
+ * Output        out = 0 where f < t, 255 elsewhere (ties give 255, Eq. 3).
+ * Pointers      img, out and every plane are DEVICE pointers owned by the
+ *               caller (e.g. torch CUDA tensors).  The library never
+ *               allocates, frees or keeps them; the single-image entry points
+ *               allocate no device memory at all.  out must not overlap img.
+ * Streams       `stream` is a hipStream_t passed as void*; NULL selects the
+ *               default (null) stream.  Every call only enqueues work and
+ *               returns; results are ready when the stream is synchronised.
+ * Errors        0 on success, a negative BZ_ERR_* code otherwise.  Arguments
+ *               are validated before anything is enqueued; on BZ_ERR_HIP the
+ *               HIP error code is kept per thread (binarize_last_hip_error).
+ *               Faults inside a kernel surface at the caller's next
+ *               synchronisation, as with any asynchronous HIP launch.
+ * Limits        1 <= win <= 255; channels in {1, 3}; H, W_img >= 1;
+ *               H * W_img * channels < 2^31; k finite; R finite and > 0.
+ * Threads       All entry points are re-entrant; calls that share a stream
+ *               are ordered by that stream.
+ */
+#ifndef BINARIZE_H
+#define BINARIZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BINARIZE_VERSION 1
+
+/* Threshold rules. */
+#define BZ_SAUVOLA 0 /* Sec. 1, Eq. 4 */
+#define BZ_NIBLACK 1 /* t = m + k s  */
+
+/* Status codes. */
+#define BZ_OK 0
+#define BZ_ERR_NULL (-1)        /* a required pointer is NULL               */
+#define BZ_ERR_SHAPE (-2)       /* H or W_img < 1, or the image is too big  */
+#define BZ_ERR_CHANNELS (-3)    /* channels not 1 or 3                      */
+#define BZ_ERR_WINDOW (-4)      /* win outside [1, 255]                     */
+#define BZ_ERR_PARAM (-5)       /* k not finite, or R not finite and > 0    */
+#define BZ_ERR_RULE (-6)        /* rule not BZ_SAUVOLA / BZ_NIBLACK         */
+#define BZ_ERR_ALIAS (-7)       /* out overlaps img (or a stats plane)      */
+#define BZ_ERR_HIP (-8)         /* the HIP runtime refused a call           */
+#define BZ_ERR_TILE (-9)        /* unsupported tile configuration           */
+#define BZ_ERR_WORKSPACE (-10)  /* workspace missing or too small           */
+
+/*
+ * binarize -- binarize one image on the null stream (Sec. 1, Eq. 1, 3, 4;
+ * Sec. 2).  img: device, H x W_img x channels; out: device, H x W_img.
+ * Returns after enqueueing the work.
+ */
+int binarize(const uint8_t *img, int H, int W_img, int channels, int win,
+             float k, float R, int rule, uint8_t *out);
+
+/* binarize_async -- as binarize, enqueued on `stream` (a hipStream_t). */
+int binarize_async(const uint8_t *img, int H, int W_img, int channels, int win,
+                   float k, float R, int rule, uint8_t *out, void *stream);
+
+/*
+ * binarize_tuned -- as binarize_async with an explicit tile shape: tile_w
+ * output columns (128 or 256; 256 needs win <= 241) by tile_h output rows
+ * (a multiple of 16, 16..4096) per workgroup.  The result is bit-identical
+ * for every tile shape; only the speed changes.  BZ_ERR_TILE otherwise.
+ */
+int binarize_tuned(const uint8_t *img, int H, int W_img, int channels, int win,
+                   float k, float R, int rule, uint8_t *out, int tile_w,
+                   int tile_h, void *stream);
+
+/*
+ * binarize_stats -- as binarize_async, and also writes the intermediate
+ * quantities of every pixel, each an H x W_img device plane (row pitch
+ * W_img): gray (u8, Eq. 1), s1 and s2 (u32 window sums of f and f^2), n
+ * (u32 in-image window count) and t (f32 threshold, Eq. 4 or Niblack).  Any
+ * plane may be NULL.  Meant for verification; slower than binarize.
+ */
+int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
+                   int win, float k, float R, int rule, uint8_t *out,
+                   uint8_t *gray, uint32_t *s1, uint32_t *s2, uint32_t *n,
+                   float *t, void *stream);
+
+/* Default tile shape binarize/binarize_async pick for a problem. */
+int binarize_default_tile(int H, int W_img, int channels, int win,
+                          int *tile_w, int *tile_h);
+
+/* Diagnostics. */
+const char *binarize_strerror(int code); /* static string, never NULL      */
+int binarize_version(void);              /* BINARIZE_VERSION               */
+int binarize_last_hip_error(void);       /* hipError_t of the last BZ_ERR_HIP
+                                            on this thread (0 if none)      */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BINARIZE_H */

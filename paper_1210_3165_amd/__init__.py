@@ -1,0 +1,165 @@
+"""Exact locally adaptive (Sauvola / Niblack) binarization on AMD MI355X.
+
+Thin Python binding over ``libbinarize.so`` (C ABI in ``include/binarize.h``):
+argument marshalling only.  Every step of the computation -- Eq. 1 gray
+conversion, exact window sums, the Eq. 4 / Niblack threshold and the Eq. 3
+decision of Mollah, Basu and Nasipuri (arXiv:1210.3165) -- runs in the HIP
+kernels.  PyTorch supplies device memory and streams; there is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
+    "default_tile", "library_path", "lib",
+]
+
+SAUVOLA = 0
+NIBLACK = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbinarize.so")
+_lib = None
+
+
+class BinarizeError(RuntimeError):
+    """A libbinarize entry point returned a negative status."""
+
+    def __init__(self, code: int, where: str):
+        msg = lib().binarize_strerror(code).decode()
+        if code == -8:
+            msg += f" (hipError {lib().binarize_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libbinarize.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_1210_3165_amd.build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+    L.binarize.argtypes = [vp, i, i, i, i, f, f, i, vp]
+    L.binarize_async.argtypes = [vp, i, i, i, i, f, f, i, vp, vp]
+    L.binarize_tuned.argtypes = [vp, i, i, i, i, f, f, i, vp, i, i, vp]
+    L.binarize_stats.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, vp, vp, vp, vp, vp]
+    L.binarize_default_tile.argtypes = [i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    for name in ("binarize", "binarize_async", "binarize_tuned", "binarize_stats",
+                 "binarize_default_tile", "binarize_version", "binarize_last_hip_error"):
+        getattr(L, name).restype = ctypes.c_int
+    L.binarize_strerror.argtypes = [i]
+    L.binarize_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _rule(rule) -> int:
+    if isinstance(rule, str):
+        r = {"sauvola": SAUVOLA, "niblack": NIBLACK}.get(rule.lower())
+        if r is None:
+            raise ValueError(f"unknown rule {rule!r}")
+        return r
+    return int(rule)
+
+
+def _check_image(img: torch.Tensor) -> tuple[int, int, int]:
+    if not isinstance(img, torch.Tensor):
+        raise TypeError("img must be a torch.Tensor")
+    if img.dtype != torch.uint8:
+        raise TypeError(f"img must be uint8, got {img.dtype}")
+    if img.device.type != "cuda":
+        raise ValueError("img must live on a GPU (device 'cuda'); there is no CPU path")
+    if not img.is_contiguous():
+        raise ValueError("img must be contiguous (rows of W*channels bytes)")
+    if img.dim() == 2:
+        return img.shape[0], img.shape[1], 1
+    if img.dim() == 3 and img.shape[2] in (1, 3):
+        return img.shape[0], img.shape[1], img.shape[2]
+    raise ValueError(f"img must be HxW or HxWx3, got {tuple(img.shape)}")
+
+
+def _stream_ptr(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return stream.cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVOLA,
+             out: torch.Tensor | None = None, tile: tuple[int, int] | None = None,
+             stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """Binarize an HxW (gray) or HxWx3 (interleaved RGB) uint8 CUDA tensor.
+
+    Returns (or fills) an HxW uint8 tensor of {0, 255} on the same device,
+    enqueued on ``stream`` (default: the current stream).  ``tile`` forces
+    the (tile_w, tile_h) workgroup tile; the result does not depend on it.
+    """
+    H, W, C = _check_image(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
+            or not out.is_contiguous():
+        raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+    L = lib()
+    with torch.cuda.device(img.device):
+        s = ctypes.c_void_p(_stream_ptr(stream, img.device))
+        if tile is None:
+            rc = L.binarize_async(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule),
+                                  _ptr(out), s)
+        else:
+            rc = L.binarize_tuned(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule),
+                                  _ptr(out), int(tile[0]), int(tile[1]), s)
+    if rc:
+        raise BinarizeError(rc, "binarize")
+    return out
+
+
+def binarize_stats(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVOLA,
+                   stream: torch.cuda.Stream | None = None) -> dict[str, torch.Tensor]:
+    """Binarize and also return every intermediate plane: gray (u8), s1, s2, n
+    (int32 views of the u32 planes), t (f32) and out (u8)."""
+    H, W, C = _check_image(img)
+    dev = img.device
+    res = {
+        "out": torch.empty((H, W), dtype=torch.uint8, device=dev),
+        "gray": torch.empty((H, W), dtype=torch.uint8, device=dev),
+        "s1": torch.empty((H, W), dtype=torch.int32, device=dev),
+        "s2": torch.empty((H, W), dtype=torch.int32, device=dev),
+        "n": torch.empty((H, W), dtype=torch.int32, device=dev),
+        "t": torch.empty((H, W), dtype=torch.float32, device=dev),
+    }
+    L = lib()
+    with torch.cuda.device(dev):
+        s = ctypes.c_void_p(_stream_ptr(stream, dev))
+        rc = L.binarize_stats(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule),
+                              _ptr(res["out"]), _ptr(res["gray"]), _ptr(res["s1"]),
+                              _ptr(res["s2"]), _ptr(res["n"]), _ptr(res["t"]), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_stats")
+    return res
+
+
+def default_tile(H: int, W: int, channels: int, win: int) -> tuple[int, int]:
+    """(tile_w, tile_h) the library picks for a problem on the current device."""
+    tw, th = ctypes.c_int(), ctypes.c_int()
+    rc = lib().binarize_default_tile(int(H), int(W), int(channels), int(win),
+                                     ctypes.byref(tw), ctypes.byref(th))
+    if rc:
+        raise BinarizeError(rc, "binarize_default_tile")
+    return tw.value, th.value

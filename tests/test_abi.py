@@ -1,0 +1,118 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol its header
+declares, and rejects bad arguments before touching the GPU (no compute
+calls are made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "binarize.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1210_3165_amd as bz
+    if not os.path.exists(bz.library_path()):
+        from paper_1210_3165_amd import build
+        build.build()
+    return bz.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)) - {"defined"})
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("binarize", "binarize_async", "binarize_stats", "binarize_strerror",
+              "binarize_version", "binarize_last_hip_error", "binarize_tuned",
+              "binarize_default_tile"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), f"libbinarize.so does not export {name}"
+
+
+def test_version_and_strerror(L):
+    assert L.binarize_version() == 1
+    for code in range(0, -11, -1):
+        s = L.binarize_strerror(code)
+        assert isinstance(s, bytes) and len(s) > 0
+    assert L.binarize_strerror(-999) == b"unknown error"
+
+
+FAKE_IN = 0x10000000
+FAKE_OUT = 0x20000000
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -1),           # null img
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, None), -1),            # null out
+    ((FAKE_IN, 0, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -2),         # H < 1
+    ((FAKE_IN, 16, -3, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -2),        # W < 1
+    ((FAKE_IN, 65536, 32768, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -2),  # 2^31 pixels
+    ((FAKE_IN, 16, 16, 4, 15, 0.5, 128.0, 0, FAKE_OUT), -3),        # RGBA
+    ((FAKE_IN, 16, 16, 1, 0, 0.5, 128.0, 0, FAKE_OUT), -4),         # win 0
+    ((FAKE_IN, 16, 16, 1, 256, 0.5, 128.0, 0, FAKE_OUT), -4),       # win 256
+    ((FAKE_IN, 16, 16, 1, 15, float("nan"), 128.0, 0, FAKE_OUT), -5),
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 0.0, 0, FAKE_OUT), -5),          # R = 0
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, float("inf"), 0, FAKE_OUT), -5),
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 2, FAKE_OUT), -6),        # rule
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_IN + 100), -7),   # out inside img
+    ((FAKE_IN, 16, 16, 3, 15, 0.5, 128.0, 0, FAKE_IN + 700), -7),   # RGB img is 768 B
+])
+def test_invalid_arguments_are_rejected_before_launch(L, args, code):
+    vp = ctypes.c_void_p
+    a = [vp(x) if i in (0, 8) else x for i, x in enumerate(args)]
+    assert L.binarize(*a) == code
+    assert L.binarize_async(*a, None) == code
+
+
+def test_stats_planes_must_not_alias(L):
+    vp = ctypes.c_void_p
+    base = [vp(FAKE_IN), 16, 16, 1, 15, 0.5, 128.0, 0, vp(FAKE_OUT)]
+    planes = [vp(0x30000000), vp(0x30000000 + 16), None, None, None]  # gray overlaps s1
+    assert L.binarize_stats(*base, *planes, None) == -7
+    planes = [None, vp(FAKE_OUT + 8), None, None, None]  # s1 overlaps out
+    assert L.binarize_stats(*base, *planes, None) == -7
+
+
+@pytest.mark.parametrize("tile", [(64, 64), (256, 8), (256, 24), (128, 8192), (0, 64)])
+def test_bad_tiles_are_rejected(L, tile):
+    vp = ctypes.c_void_p
+    rc = L.binarize_tuned(vp(FAKE_IN), 64, 64, 1, 15, 0.5, 128.0, 0, vp(FAKE_OUT),
+                          tile[0], tile[1], None)
+    assert rc == -9
+
+
+def test_wide_window_needs_narrow_tile(L):
+    vp = ctypes.c_void_p
+    # a 255-wide window does not fit the 256-column tile's LDS budget
+    rc = L.binarize_tuned(vp(FAKE_IN), 64, 64, 1, 255, 0.5, 128.0, 0, vp(FAKE_OUT), 256, 64, None)
+    assert rc == -9
+
+
+def test_default_tile_shapes(L):
+    tw, th = ctypes.c_int(), ctypes.c_int()
+    for win in (1, 15, 31, 61, 101, 151, 201, 255):
+        assert L.binarize_default_tile(4096, 4096, 1, win, ctypes.byref(tw), ctypes.byref(th)) == 0
+        assert tw.value in (128, 256)
+        assert th.value % 16 == 0 and 16 <= th.value <= 4096
+    assert L.binarize_default_tile(100, 100, 1, 255, ctypes.byref(tw), ctypes.byref(th)) == 0
+    assert tw.value == 128
+    assert L.binarize_default_tile(100, 100, 2, 15, ctypes.byref(tw), ctypes.byref(th)) == -3
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    import paper_1210_3165_amd as bz
+    with pytest.raises(ValueError):
+        bz.binarize(torch.zeros((8, 8), dtype=torch.uint8), 3, 0.5)
+    with pytest.raises(TypeError):
+        bz.binarize(torch.zeros((8, 8), dtype=torch.float32), 3, 0.5)
