@@ -58,13 +58,8 @@ int device_cus() {
 }
 
 void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
-    LdsPlan l;
-    int w = 256;
-    if (!plan_lds(256, win, &l)) {
-        w = 128;
-        plan_lds(128, win, &l);
-    }
-    int per_cu = kMaxLds / l.bytes;
+    const int w = tile_fits(256, win) ? 256 : 128;
+    int per_cu = kMaxLds / tile_lds_bytes(w, win);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 4) per_cu = 4;  // 4 x 8 waves fill a CU
     const long target = (long)cus * per_cu;
@@ -80,14 +75,15 @@ void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
 
 struct Plan {
     int tile_w, tile_h;
-    LdsPlan lds;
+    int lds_bytes;
     int tiles_x, tiles_y;
 };
 
 int make_plan(int H, int W, int win, int tile_w, int tile_h, Plan *p) {
     if (tile_w != 128 && tile_w != 256) return BZ_ERR_TILE;
     if (tile_h < kRowsPerStep || tile_h > 4096 || tile_h % kRowsPerStep) return BZ_ERR_TILE;
-    if (!plan_lds(tile_w, win, &p->lds)) return BZ_ERR_TILE;
+    if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
+    p->lds_bytes = tile_lds_bytes(tile_w, win);
     p->tile_w = tile_w;
     p->tile_h = tile_h;
     p->tiles_x = (W + tile_w - 1) / tile_w;
@@ -113,11 +109,8 @@ void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int win, float k, 
     a->tile_h = p.tile_h;
     a->tiles_x = p.tiles_x;
     a->n_tiles = p.tiles_x * p.tiles_y;
-    a->rp = p.lds.rp;
-    a->depth = p.lds.depth;
-    a->vp = p.lds.vp;
-    a->off_v1 = p.lds.off_v1;
-    a->off_v2 = p.lds.off_v2;
+    a->rp = ring_pitch(p.tile_w, win);
+    a->depth = ring_depth(win);
 }
 
 template <int TW, int C, int RULE, bool STATS>
@@ -185,7 +178,7 @@ int run(const uint8_t *img, int H, int W, int C, int win, float k, float R, int 
         a.n = n;
         a.t = t;
     }
-    return launch(a, p.tile_w, C, rule, stats, p.lds.bytes, (hipStream_t)stream);
+    return launch(a, p.tile_w, C, rule, stats, p.lds_bytes, (hipStream_t)stream);
 }
 
 }  // namespace

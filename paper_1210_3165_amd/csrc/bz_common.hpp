@@ -1,7 +1,13 @@
-// bz_common.hpp -- launch arguments shared by the host dispatcher and the
-// gfx950 kernels of libbinarize.
+// bz_common.hpp -- launch arguments and LDS plan shared by the host
+// dispatcher and the gfx950 kernels of libbinarize.
 #pragma once
 #include <stdint.h>
+
+#if defined(__HIPCC__)
+#define BZ_HD __host__ __device__
+#else
+#define BZ_HD
+#endif
 
 namespace bz {
 
@@ -9,10 +15,10 @@ namespace bz {
 // pass gives every thread one LDS column; the horizontal pass gives each of
 // the RB output rows of a step TPR = 32 threads.
 constexpr int kThreads = 512;
-constexpr int kRowsPerStep = 16;                   // RB
+constexpr int kRowsPerStep = 16;                         // RB
 constexpr int kThreadsPerRow = kThreads / kRowsPerStep;  // TPR = 32
-constexpr int kMaxCols = kThreads;                 // LDS columns per tile
-constexpr int kMaxLds = 160 * 1024;                // gfx950 LDS per workgroup
+constexpr int kMaxCols = kThreads;                       // LDS columns per tile
+constexpr int kMaxLds = 160 * 1024;                      // gfx950 LDS per workgroup
 
 // One page as the tile kernel sees it.  All geometry that depends only on the
 // page and the tile shape is computed once on the host.
@@ -26,45 +32,44 @@ struct PageArgs {
     uint32_t *n;
     float *t;
     int H, W;
-    int win, lo, hi;     // window side and its extent above/left (lo) and below/right (hi)
-    float k;             // Niblack k
-    float c1, c2;        // Sauvola: c1 = 1 - k, c2 = k / R
-    int tile_h;          // output rows per workgroup (multiple of kRowsPerStep)
-    int tiles_x;         // tiles per image row
-    int n_tiles;         // tiles_x * tiles_y
-    int rp;              // LDS ring row pitch in bytes (multiple of 16)
-    int depth;           // ring depth in rows = win + kRowsPerStep
-    int vp;              // swizzle class pitch of the window-sum rows
-    int off_v1, off_v2;  // byte offsets of the V1 / V2 row blocks in LDS
+    int win, lo, hi;  // window side and its extent above/left (lo) and below/right (hi)
+    float k;          // Niblack k
+    float c1, c2;     // Sauvola: c1 = 1 - k, c2 = k / R
+    int tile_h;       // output rows per workgroup (multiple of kRowsPerStep)
+    int tiles_x;      // tiles per image row
+    int n_tiles;      // tiles_x * tiles_y
+    int rp;           // LDS ring row pitch in bytes (multiple of 16)
+    int depth;        // ring depth in rows
 };
 
-// LDS footprint and swizzle pitch of one tile configuration.
-struct LdsPlan {
-    int rp, depth, vp, off_v1, off_v2, bytes;
-};
+BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+// Ring geometry.  rp covers the tile, its halo and up to 16 columns of
+// alignment slack.  depth holds every row one step touches (win + 16) and, when
+// the window reaches less than 16 rows up, enough extra rows that the slots
+// refilled at the start of a step held no row the previous step still reads
+// as a window centre: depth >= hi + 32.
+BZ_HD inline int ring_pitch(int tile_w, int win) { return round_up(tile_w + win + 15, 16); }
+BZ_HD inline int ring_depth(int win) {
+    const int hi = win - 1 - win / 2;
+    return (win + kRowsPerStep > hi + 2 * kRowsPerStep) ? win + kRowsPerStep : hi + 2 * kRowsPerStep;
+}
+BZ_HD inline int ring_bytes(int tile_w, int win) {
+    return round_up(ring_depth(win) * ring_pitch(tile_w, win) + 16, 16);
+}
+// Width of the Vb rows: the tile, or the whole first window if that is wider.
+BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
+// LDS layout: ring | Va1 [RB][TW] u16 | Vb1 [RB][vbw] u16 | Va2 [RB][TW] u32 | Vb2 [RB][vbw] u32
+BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
+    const int w = vb_width(tile_w, win);
+    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4);
+}
 
-// tile_w output columns, window win.  Returns false if it cannot fit.
-inline bool plan_lds(int tile_w, int win, LdsPlan *p) {
-    const int opt = tile_w / kThreadsPerRow;  // outputs per thread per row
-    const int rp = round_up(tile_w + win + 15, 16);
-    if (rp > kMaxCols) return false;
-    const int depth = win + kRowsPerStep;
-    // class pitch vp: every class holds rp/opt columns; opt*vp = 16 (mod 64)
-    // keeps the 4 rows of a wave on different LDS banks.
-    int vp = (rp + opt - 1) / opt;
-    while ((opt * vp) % 64 != 16) ++vp;
-    const int ring = round_up(depth * rp + 16, 16);
-    const int v1 = round_up(kRowsPerStep * opt * vp * 2, 16);
-    const int v2 = kRowsPerStep * opt * vp * 4;
-    p->rp = rp;
-    p->depth = depth;
-    p->vp = vp;
-    p->off_v1 = ring;
-    p->off_v2 = ring + v1;
-    p->bytes = ring + v1 + v2;
-    return p->bytes <= kMaxLds;
+// Does this tile configuration fit the hardware?
+inline bool tile_fits(int tile_w, int win) {
+    if (tile_w != 128 && tile_w != 256) return false;
+    if (ring_pitch(tile_w, win) > kMaxCols) return false;
+    return tile_lds_bytes(tile_w, win) <= kMaxLds;
 }
 
 }  // namespace bz

@@ -6,15 +6,20 @@
 // integer window sums of f and f^2, built separably inside the tile:
 //
 //   ring    LDS ring of gray rows (Sec. 1 Eq. 1 applied while staging), one
-//           row per image row, win + 16 rows deep, tile plus halo wide.  Each
-//           input byte is read from HBM once per tile.
+//           row per image row, at least win + 16 rows deep, tile plus halo
+//           wide.  Each
+//           input byte is read from HBM once per tile; the rows of the next
+//           step are loaded into registers while the current step computes.
 //   V pass  one thread per LDS column slides the vertical window down the
 //           tile: V(y) = V(y-1) + f(y+hi) - f(y-lo-1) for V1 = sum f and
 //           V2 = sum f^2 (f_in^2 - f_out^2 formed as (f_in - f_out)(f_in + f_out)).
-//   H pass  32 threads per output row turn V into the horizontal window sums
-//           S(x) = S(x-1) + V(x+hi) - V(x-lo-1): per-thread prefix of the
-//           differences, an exclusive scan across the 32 threads and the sum
-//           of the first window as the row's starting value.
+//           Each V row is stored twice, shifted so that output column x finds
+//           the column entering its window (Va[x]) and the one leaving it
+//           (Vb[x]) at the same index.
+//   H pass  32 threads per output row, 8 (or 4) consecutive outputs each:
+//           S(x) = S(x-1) + Va[x] - Vb[x], i.e. a per-thread prefix of the
+//           differences, a DPP scan across the 32 threads, and the window sum
+//           left of the tile as the starting value.
 //   decide  exact D = n S2 - S1^2 in fp64, then the Eq. 4 / Niblack threshold
 //           compared with f in fp32 after scaling both sides by n (Eq. 3).
 //
@@ -47,137 +52,188 @@ __device__ __forceinline__ uint32_t byte_at(const uint32_t (&w)[N], int i) {
     return (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
 }
 
-// 16 gray levels of image columns [xs, xs + 16) of one image row; columns
-// outside [0, W) read as 0.  Only 4-byte words holding at least one byte of
-// the row are touched, so no access leaves the caller's buffer's pages.
-template <int C>
-__device__ __forceinline__ uint4 load_gray16(const uint8_t *__restrict__ rowp, int xs, int W);
+// ---------------------------------------------------------------- staging
+//
+// A staging job is 16 consecutive pixels of one image row.  Its raw bytes are
+// fetched into registers (RawChunk) one step ahead of use and reduced to 16
+// gray levels when written into the ring.
 
-template <>
-__device__ __forceinline__ uint4 load_gray16<1>(const uint8_t *__restrict__ rowp, int xs, int W) {
-    if (xs >= 0 && xs + 16 <= W) {
-        const uint8_t *p = rowp + xs;
-        const uintptr_t ad = (uintptr_t)p;
-        if ((ad & 15) == 0) return *(const uint4 *)p;
-        const uint32_t sh = (uint32_t)(ad & 3);
-        const uint32_t *q = (const uint32_t *)(ad - sh);
-        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
-        const uint32_t w4 = sh ? q[4] : 0u;
-        return make_uint4(align_bytes(w1, w0, sh), align_bytes(w2, w1, sh),
-                          align_bytes(w3, w2, sh), align_bytes(w4, w3, sh));
-    }
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
+template <int C>
+struct RawChunk {
+    static constexpr int NW = C == 1 ? 5 : 13;  // aligned words covering 16*C bytes + 1
+    uint32_t w[NW];
+    uint32_t sh;  // byte offset of the chunk's first byte in w[0]
+};
+
+// Issue the loads for the raw bytes of image columns [xs, xs + 16) of one row.
+// Nothing reads the loaded registers until chunk_gray, one step later, so the
+// loads stay in flight while the tile computes.  Word i nominally sits at
+// (first byte & ~3) + 4 i; on tiles that reach past the image's left or right
+// edge (clamp == true) every word address is clamped into the words that hold
+// at least one byte of this row, so no access leaves the caller's buffer.
+// Bytes that belong to columns outside [0, W) are discarded by chunk_gray.
+template <int C>
+__device__ __forceinline__ void fetch_chunk(RawChunk<C> &k, const uint8_t *__restrict__ rowp, int xs, int W,
+                                            bool clamp) {
+    const uintptr_t ad = (uintptr_t)rowp + (uintptr_t)(intptr_t)(C * xs);
+    k.sh = (uint32_t)(ad & 3);
+    uintptr_t q = ad - k.sh;
+    if (clamp) {
+        const uintptr_t first = (uintptr_t)rowp & ~(uintptr_t)3;
+        const uintptr_t last = ((uintptr_t)rowp + (uintptr_t)(C * W) - 1) & ~(uintptr_t)3;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int c = xs + i;
-        if (c >= 0 && c < W) w[i >> 2] |= (uint32_t)rowp[c] << (8 * (i & 3));
+        for (int i = 0; i < RawChunk<C>::NW; ++i) {
+            uintptr_t qi = q + 4 * i;
+            qi = qi < first ? first : (qi > last ? last : qi);
+            k.w[i] = *(const uint32_t *)qi;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RawChunk<C>::NW; ++i) k.w[i] = ((const uint32_t *)q)[i];
     }
-    return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-template <>
-__device__ __forceinline__ uint4 load_gray16<3>(const uint8_t *__restrict__ rowp, int xs, int W) {
-    uint32_t o[4] = {0u, 0u, 0u, 0u};
-    if (xs >= 0 && xs + 16 <= W) {
-        const uint8_t *p = rowp + 3 * xs;
-        const uintptr_t ad = (uintptr_t)p;
-        const uint32_t sh = (uint32_t)(ad & 3);
-        const uint32_t *q = (const uint32_t *)(ad - sh);
-        uint32_t w[13];
+// 16 gray levels from a fetched chunk; columns outside [0, W) become 0.
+template <int C>
+__device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W, bool clamp) {
+    constexpr int NB = C == 1 ? 4 : 12;
+    uint32_t b[NB];
 #pragma unroll
-        for (int i = 0; i < 12; ++i) w[i] = q[i];
-        w[12] = sh ? q[12] : 0u;
-        uint32_t b[12];
+    for (int i = 0; i < NB; ++i) b[i] = align_bytes(k.w[i + 1], k.w[i], k.sh);
+    uint32_t o[4];
+    if (C == 1) {
 #pragma unroll
-        for (int i = 0; i < 12; ++i) b[i] = align_bytes(w[i + 1], w[i], sh);
+        for (int i = 0; i < 4; ++i) o[i] = b[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = 0u;
 #pragma unroll
         for (int px = 0; px < 16; ++px)
-            o[px >> 2] |= gray_of(byte_at(b, 3 * px), byte_at(b, 3 * px + 1),
-                                  byte_at(b, 3 * px + 2)) << (8 * (px & 3));
-    } else {
+            o[px >> 2] |= gray_of(byte_at(b, 3 * px), byte_at(b, 3 * px + 1), byte_at(b, 3 * px + 2))
+                          << (8 * (px & 3));
+    }
+    if (clamp) {
 #pragma unroll
         for (int px = 0; px < 16; ++px) {
             const int c = xs + px;
-            if (c >= 0 && c < W) {
-                const uint8_t *p = rowp + 3 * c;
-                o[px >> 2] |= gray_of(p[0], p[1], p[2]) << (8 * (px & 3));
-            }
+            if (c < 0 || c >= W) o[px >> 2] &= ~(0xffu << (8 * (px & 3)));
         }
     }
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Stage `cnt` consecutive image rows starting at row0 into ring slots
-// slot0, slot0 + 1, ... (mod depth), LDS columns [0, rp) = image columns
-// [xr0, xr0 + rp).  Rows outside the image are stored as zeros.
+// The job of this thread for a block of up to 16 rows: row i = job / nq of
+// the block, chunk q = job % nq (nq = rp / 16 chunks per row).  rp <= 512
+// gives at most one job per thread.  Rows outside the image load a clamped
+// row (always a valid address) and store zeros.
 template <int C>
-__device__ __forceinline__ void stage_rows(const PageArgs &a, uint8_t *ring, int row0, int cnt,
-                                           int slot0, int xr0) {
-    const int nq = a.rp >> 4;
-    const int jobs = cnt * nq;
-    for (int job = threadIdx.x; job < jobs; job += kThreads) {
-        const int i = job / nq;
-        const int q = job - i * nq;
-        const int row = row0 + i;
-        int sl = slot0 + i;
-        if (sl >= a.depth) sl -= a.depth;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (row >= 0 && row < a.H)
-            v = load_gray16<C>(a.img + (size_t)row * (size_t)a.W * C, xr0 + 16 * q, a.W);
-        *(uint4 *)(ring + sl * a.rp + 16 * q) = v;
+struct Stager {
+    RawChunk<C> k;
+    int job_row, job_q;  // job_row < 0: this thread has no job
+    bool in_image;
+
+    __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
+        const int nq = a.rp >> 4;
+        const int job = (int)threadIdx.x;
+        job_row = -1;
+        if (job < nrows * nq) {
+            job_row = job / nq;
+            job_q = job - job_row * nq;
+            const int row = row0 + job_row;
+            in_image = row >= 0 && row < a.H;
+            const int rc = min(max(row, 0), a.H - 1);
+            fetch_chunk<C>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
+        }
     }
+
+    __device__ __forceinline__ void store(const PageArgs &a, uint8_t *ring, int slot0, int xr0,
+                                          bool clamp) const {
+        if (job_row < 0) return;
+        int sl = slot0 + job_row;
+        if (sl >= a.depth) sl -= a.depth;
+        uint4 v = chunk_gray<C>(k, xr0 + 16 * job_q, a.W, clamp);
+        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
+        *(uint4 *)(ring + sl * a.rp + 16 * job_q) = v;
+    }
+};
+
+// ---------------------------------------------------------------- scans
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_src(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, true);
 }
 
-// Sum over the 32 lanes of a row group (all lanes end with the total).
-__device__ __forceinline__ uint32_t group_sum(uint32_t v) {
-#pragma unroll
-    for (int m = kThreadsPerRow / 2; m >= 1; m >>= 1) v += (uint32_t)__shfl_xor((int)v, m, kThreadsPerRow);
+// Inclusive prefix sum within each 32-lane half of the wave: row_shr 1, 2,
+// 4, 8 inside each 16-lane DPP row, then row_bcast:15 carries the total of
+// rows 0 and 2 into rows 1 and 3.  Unsigned wrap-around is harmless: every
+// final window sum is below 2^32.
+__device__ __forceinline__ uint32_t scan32(uint32_t v) {
+    v += dpp_src<0x111>(v);
+    v += dpp_src<0x112>(v);
+    v += dpp_src<0x114>(v);
+    v += dpp_src<0x118>(v);
+    v += dpp_src<0x142, 0xa>(v);
     return v;
 }
 
-// Exclusive prefix sum over the 32 lanes of a row group (lane s gets the sum
-// of lanes 0..s-1).  Unsigned wrap-around is harmless: every final window sum
-// is below 2^32.
-__device__ __forceinline__ uint32_t group_excl_scan(uint32_t v, int s) {
-    uint32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < kThreadsPerRow; d <<= 1) {
-        const uint32_t o = (uint32_t)__shfl_up((int)incl, d, kThreadsPerRow);
-        if (s >= d) incl += o;
-    }
-    return incl - v;
+// Total of the 32-lane half this lane belongs to, given its inclusive scan.
+__device__ __forceinline__ uint32_t half_total(uint32_t incl) {
+    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)incl, 31);
+    const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    return (threadIdx.x & 32) ? t1 : t0;
+}
+
+// ---------------------------------------------------------------- decision
+
+// Per-row quantities of the decision when n is the same for the whole row
+// segment (n = nx * ny with nx = win inside the image).
+struct RowN {
+    double nd;
+    float nf, c1n;
+    uint32_t n;
+};
+
+__device__ __forceinline__ RowN row_n(const PageArgs &a, uint32_t n) {
+    RowN q;
+    q.n = n;
+    q.nd = (double)n;
+    q.nf = (float)n;
+    q.c1n = a.c1 * q.nf;
+    return q;
 }
 
 // Eq. 3 decision for one pixel from its exact window sums.
 //   Sauvola (Eq. 4): f < m (1 + k (s/R - 1)) with m = S1/n, s = sqrt(D)/n
-//     <=> n^2 f < S1 (n (1 - k) + (k/R) sqrt(D))       (n > 0)
+//     <=> (n f) n < S1 (n (1 - k) + (k/R) sqrt(D))       (n > 0)
 //   Niblack: f < m + k s  <=>  n f - S1 < k sqrt(D)
 // D = n S2 - S1^2 is formed exactly in fp64 (every term is an integer below
-// 2^53).  n f is exact in fp32 (below 2^24), so a window of constant gray
-// level (D = 0) decides ties exactly: Niblack gives f = t and therefore 255.
+// 2^53) and n f exactly in integers, so a window of constant gray level
+// (D = 0) decides ties exactly: Niblack gives f = t and therefore 255.
 template <int RULE>
 __device__ __forceinline__ uint32_t decide(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
-                                           uint32_t n, float *t_out) {
+                                           const RowN &q, float *t_out) {
     const double s1d = (double)S1;
-    const double D = __builtin_fma((double)n, (double)S2, -(s1d * s1d));
+    const double D = __builtin_fma(q.nd, (double)S2, -(s1d * s1d));
     const float sq = __builtin_amdgcn_sqrtf((float)D);
-    const float nf = (float)n;
+    const uint32_t nfi = q.n * f;  // < 2^24
     uint32_t g;
     if (RULE == 0) {
-        const float lhs = (float)(n * f) * nf;
-        const float rhs = (float)S1 * __builtin_fmaf(a.c2, sq, a.c1 * nf);
+        const float lhs = (float)nfi * q.nf;
+        const float rhs = (float)S1 * __builtin_fmaf(a.c2, sq, q.c1n);
         g = lhs < rhs ? 0u : 255u;
     } else {
-        const int L = (int)(n * f) - (int)S1;
-        g = (float)L < a.k * sq ? 0u : 255u;
+        g = (float)((int)nfi - (int)S1) < a.k * sq ? 0u : 255u;
     }
     if (t_out) {  // verification only: t itself, Eq. 4 / Niblack in fp32
-        const float m = (float)S1 / nf;
-        const float s = sq / nf;
+        const float m = (float)S1 / q.nf;
+        const float s = sq / q.nf;
         *t_out = (RULE == 0) ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
     }
     return g;
 }
+
+// ---------------------------------------------------------------- output
 
 // Store OPT output bytes (packed little-endian in w) at columns [xs, xs+OPT)
 // of an output row, skipping columns >= W.
@@ -214,13 +270,43 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
+template <int OPT>
+__device__ __forceinline__ void load_u16(const uint16_t *p, uint32_t (&v)[OPT]) {
+    if (OPT == 8) {
+        const uint4 q = *(const uint4 *)p;
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = w[i] & 0xffffu;
+            v[2 * i + 1] = w[i] >> 16;
+        }
+    } else {
+        const uint2 q = *(const uint2 *)p;
+        v[0] = q.x & 0xffffu;
+        v[1] = q.x >> 16;
+        v[2] = q.y & 0xffffu;
+        v[3] = q.y >> 16;
+    }
+}
+
+template <int OPT>
+__device__ __forceinline__ void load_u32(const uint32_t *p, uint32_t (&v)[OPT]) {
+#pragma unroll
+    for (int i = 0; i < OPT / 4; ++i) {
+        const uint4 q = *(const uint4 *)(p + 4 * i);
+        v[4 * i] = q.x;
+        v[4 * i + 1] = q.y;
+        v[4 * i + 2] = q.z;
+        v[4 * i + 3] = q.w;
+    }
+}
+
 template <int TW, int C, int RULE, bool STATS>
 __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_t *smem) {
     constexpr int RB = kRowsPerStep;
     constexpr int TPR = kThreadsPerRow;
     constexpr int OPT = TW / TPR;  // outputs per thread per row (4 or 8)
     static_assert(OPT == 4 || OPT == 8, "tile width must be 128 or 256");
-    constexpr int LOG_OPT = OPT == 8 ? 3 : 2;
 
     const int tid = threadIdx.x;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -229,21 +315,38 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const int lo = a.lo, hi = a.hi, win = a.win;
     const int xr0 = floor16(X0 - lo - 1);  // image column of LDS column 0
     const int off0 = X0 - lo - xr0;        // LDS column of the first window column, 1..16
-    const int rp = a.rp, depth = a.depth, vp = a.vp;
-    const int vrow = OPT * vp;
+    const int rp = a.rp, depth = a.depth;
+    const int vbw = vb_width(TW, win);
     uint8_t *ring = smem;
-    uint16_t *V1 = (uint16_t *)(smem + a.off_v1);
-    uint32_t *V2 = (uint32_t *)(smem + a.off_v2);
+    uint16_t *Va1 = (uint16_t *)(smem + ring_bytes(TW, win));
+    uint16_t *Vb1 = Va1 + RB * TW;
+    uint32_t *Va2 = (uint32_t *)(Vb1 + RB * vbw);
+    uint32_t *Vb2 = Va2 + RB * TW;
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
-    auto vpos = [&](int c) { return (c & (OPT - 1)) * vp + (c >> LOG_OPT); };
+    // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
+    // extra word a chunk may read past its last byte all lie inside the row.
+    const bool clamp = xr0 < 0 || xr0 + rp + 4 > a.W;
 
     // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1
-    stage_rows<C>(a, ring, base, win, 0, xr0);
+    {
+        Stager<C> st;
+        for (int r0 = 0; r0 < win; r0 += RB) {
+            const int nr = min(RB, win - r0);
+            st.fetch(a, base + r0, nr, xr0, clamp);
+            st.store(a, ring, r0, xr0, clamp);
+        }
+    }
+    Stager<C> pre;  // rows of the next step, in flight while this one computes
+    pre.fetch(a, Y0 + hi, RB, xr0, clamp);
     __syncthreads();
-    const int c = tid;
+
+    const int c = tid;  // V-pass column
     const bool vcol = c < rp;
-    const int cpos = vpos(c);
+    const int ia = c - off0 - win + 1;  // Va index of column c
+    const int ib = c - off0 + 1;        // Vb index of column c
+    const bool wa = vcol && ia >= 0 && ia < TW;
+    const bool wb = vcol && ib >= 0 && ib < vbw;
     uint32_t v1 = 0, v2 = 0;
     if (vcol) {
         for (int i = 0; i < win; ++i) {
@@ -254,11 +357,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
+    const bool x_inside = X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1;
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
-        __syncthreads();
-        stage_rows<C>(a, ring, y0 + hi, RB, s_in, xr0);
+        // Rows of this step go into ring slots that held rows leaving the
+        // window in the previous step; no thread reads those any more.
+        pre.store(a, ring, s_in, xr0, clamp);
+        if (y0 + RB < Yend) pre.fetch(a, y0 + RB + hi, RB, xr0, clamp);
         __syncthreads();
 
         // ---- vertical pass: one LDS column per thread, RB rows
@@ -270,81 +376,109 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 const int d = fn - fo;
                 v1 += (uint32_t)d;
                 v2 += (uint32_t)(d * (fn + fo));
-                V1[r * vrow + cpos] = (uint16_t)v1;
-                V2[r * vrow + cpos] = v2;
+                if (wa) {
+                    Va1[r * TW + ia] = (uint16_t)v1;
+                    Va2[r * TW + ia] = v2;
+                }
+                if (wb) {
+                    Vb1[r * vbw + ib] = (uint16_t)v1;
+                    Vb2[r * vbw + ib] = v2;
+                }
                 se = (se + 1 == depth) ? 0 : se + 1;
                 sx = (sx + 1 == depth) ? 0 : sx + 1;
             }
         }
         __syncthreads();
 
-        // ---- horizontal pass + threshold: 32 threads per output row
+        // ---- horizontal pass + threshold: 32 threads per output row.
+        // Every group runs (rows past the tile compute on stale LDS data and
+        // store nothing) so the cross-lane scans see full 32-lane halves.
         const int y = y0 + hr;
-        if (y < Yend) {  // uniform across each 32-lane row group
-            const uint16_t *V1r = V1 + hr * vrow;
-            const uint32_t *V2r = V2 + hr * vrow;
-            // starting value: the window sum one column left of the tile
-            uint32_t h1 = 0, h2 = 0;
-            for (int cc = off0 - 1 + hs; cc < off0 - 1 + win; cc += TPR) {
-                const int p = vpos(cc);
-                h1 += V1r[p];
-                h2 += V2r[p];
-            }
-            h1 = group_sum(h1);
-            h2 = group_sum(h2);
-            uint32_t E1[OPT], E2[OPT];
-            uint32_t a1 = 0, a2 = 0;
+        const uint16_t *va1 = Va1 + hr * TW + hs * OPT;
+        const uint16_t *vb1 = Vb1 + hr * vbw + hs * OPT;
+        const uint32_t *va2 = Va2 + hr * TW + hs * OPT;
+        const uint32_t *vb2 = Vb2 + hr * vbw + hs * OPT;
+        uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
+        load_u16<OPT>(va1, A1);
+        load_u16<OPT>(vb1, B1);
+        load_u32<OPT>(va2, A2);
+        load_u32<OPT>(vb2, B2);
+        // starting value: window sum one column left of the tile
+        uint32_t h1 = 0, h2 = 0;
+        for (int i = hs; i < win; i += TPR) {
+            h1 += Vb1[hr * vbw + i];
+            h2 += Vb2[hr * vbw + i];
+        }
+        // running sums of the entering-minus-leaving columns
+        uint32_t E1[OPT], E2[OPT];
+        uint32_t a1 = 0, a2 = 0;
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            a1 += A1[j] - B1[j];
+            a2 += A2[j] - B2[j];
+            E1[j] = a1;
+            E2[j] = a2;
+        }
+        const uint32_t s1i = scan32(a1), s2i = scan32(a2);
+        const uint32_t h1i = scan32(h1), h2i = scan32(h2);
+        const uint32_t b1 = half_total(h1i) + s1i - a1;
+        const uint32_t b2 = half_total(h2i) + s2i - a2;
+
+        // gray levels of the output row (centre of the window)
+        const int fo = ((y - base) % depth) * rp + off0 + lo + hs * OPT;
+        const uint32_t fsh = (uint32_t)(fo & 3);
+        const uint32_t *fq = (const uint32_t *)(smem + (fo & ~3));
+        uint32_t fw[OPT / 4];
+#pragma unroll
+        for (int i = 0; i < OPT / 4; ++i) fw[i] = align_bytes(fq[i + 1], fq[i], fsh);
+
+        const int ny = min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
+        const int xs = X0 + hs * OPT;
+        uint32_t ow[OPT / 4];
+#pragma unroll
+        for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
+        float tv[OPT];
+        if (x_inside) {
+            const RowN q = row_n(a, (uint32_t)(win * ny));
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
-                const int xj = hs * OPT + j;
-                const int pa = vpos(off0 + xj + win - 1), pb = vpos(off0 + xj - 1);
-                a1 += (uint32_t)V1r[pa] - (uint32_t)V1r[pb];
-                a2 += V2r[pa] - V2r[pb];
-                E1[j] = a1;
-                E2[j] = a2;
+                const uint32_t g = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
+                                                STATS ? &tv[j] : nullptr);
+                ow[j >> 2] |= g << (8 * (j & 3));
             }
-            const uint32_t b1 = h1 + group_excl_scan(a1, hs);
-            const uint32_t b2 = h2 + group_excl_scan(a2, hs);
-
-            // gray levels of the output row (centre of the window)
-            const int fo = ((y - base) % depth) * rp + off0 + lo + hs * OPT;
-            const uint32_t fsh = (uint32_t)(fo & 3);
-            const uint32_t *fq = (const uint32_t *)(smem + (fo & ~3));
-            uint32_t fw[OPT / 4];
-#pragma unroll
-            for (int i = 0; i < OPT / 4; ++i) fw[i] = align_bytes(fq[i + 1], fq[i], fsh);
-
-            const int ny = min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
-            uint32_t ow[OPT / 4];
-#pragma unroll
-            for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
-            const int xs = X0 + hs * OPT;
+        } else {
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int X = xs + j;
-                const uint32_t S1 = b1 + E1[j], S2 = b2 + E2[j];
                 const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
-                const uint32_t n = (uint32_t)(nx * ny);
-                const uint32_t f = byte_at(fw, j);
-                float t;
-                const uint32_t g = decide<RULE>(a, f, S1, S2, n, STATS ? &t : nullptr);
+                const RowN q = row_n(a, (uint32_t)(nx * ny));
+                const uint32_t g = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
+                                                STATS ? &tv[j] : nullptr);
                 ow[j >> 2] |= g << (8 * (j & 3));
-                if (STATS && X < a.W) {
+            }
+        }
+        if (y < Yend) {
+            store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
+            if (STATS) {
+#pragma unroll
+                for (int j = 0; j < OPT; ++j) {
+                    const int X = xs + j;
+                    if (X >= a.W) continue;
                     const size_t i = (size_t)y * a.W + X;
-                    if (a.gray) a.gray[i] = (uint8_t)f;
-                    if (a.s1) a.s1[i] = S1;
-                    if (a.s2) a.s2[i] = S2;
-                    if (a.n) a.n[i] = n;
-                    if (a.t) a.t[i] = t;
+                    const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
+                    if (a.gray) a.gray[i] = (uint8_t)byte_at(fw, j);
+                    if (a.s1) a.s1[i] = b1 + E1[j];
+                    if (a.s2) a.s2[i] = b2 + E2[j];
+                    if (a.n) a.n[i] = (uint32_t)(nx * ny);
+                    if (a.t) a.t[i] = tv[j];
                 }
             }
-            store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
         }
     }
 }
 
 template <int TW, int C, int RULE, bool STATS>
-__global__ void __launch_bounds__(kThreads) bz_page_kernel(PageArgs a) {
+__global__ void __launch_bounds__(kThreads, 4) bz_page_kernel(PageArgs a) {
     extern __shared__ uint4 bz_lds[];
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     process_tile<TW, C, RULE, STATS>(a, tile, (uint8_t *)bz_lds);
