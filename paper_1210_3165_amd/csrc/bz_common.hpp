@@ -59,10 +59,12 @@ BZ_HD inline int ring_bytes(int tile_w, int win) {
 }
 // Width of the Vb rows: the tile, or the whole first window if that is wider.
 BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
-// LDS layout: ring | Va1 [RB][TW] u16 | Vb1 [RB][vbw] u16 | Va2 [RB][TW] u32 | Vb2 [RB][vbw] u32
+// LDS layout: ring | Va1 [RB][TW] u16 | Vb1 [RB][vbw] u16 | Va2 [RB][TW] u32 |
+// Vb2 [RB][vbw] u32 | 16-byte trash slot (target of writes that fall outside
+// Va / Vb, so the vertical pass needs no branches)
 BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
     const int w = vb_width(tile_w, win);
-    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4);
+    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4) + 16;
 }
 
 // Does this tile configuration fit the hardware?

@@ -129,16 +129,17 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
 template <int C>
 struct Stager {
     RawChunk<C> k;
-    int job_row, job_q;  // job_row < 0: this thread has no job
+    int job_row, job_q;  // job_row >= kRowsPerStep: this thread has no job
     bool in_image;
 
-    __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
+    __device__ __forceinline__ void init(const PageArgs &a) {
         const int nq = a.rp >> 4;
-        const int job = (int)threadIdx.x;
-        job_row = -1;
-        if (job < nrows * nq) {
-            job_row = job / nq;
-            job_q = job - job_row * nq;
+        job_row = (int)threadIdx.x / nq;
+        job_q = (int)threadIdx.x - job_row * nq;
+    }
+
+    __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
+        if (job_row < nrows) {
             const int row = row0 + job_row;
             in_image = row >= 0 && row < a.H;
             const int rc = min(max(row, 0), a.H - 1);
@@ -146,9 +147,9 @@ struct Stager {
         }
     }
 
-    __device__ __forceinline__ void store(const PageArgs &a, uint8_t *ring, int slot0, int xr0,
+    __device__ __forceinline__ void store(const PageArgs &a, uint8_t *ring, int slot0, int nrows, int xr0,
                                           bool clamp) const {
-        if (job_row < 0) return;
+        if (job_row >= nrows) return;
         int sl = slot0 + job_row;
         if (sl >= a.depth) sl -= a.depth;
         uint4 v = chunk_gray<C>(k, xr0 + 16 * job_q, a.W, clamp);
@@ -211,26 +212,26 @@ __device__ __forceinline__ RowN row_n(const PageArgs &a, uint32_t n) {
 // 2^53) and n f exactly in integers, so a window of constant gray level
 // (D = 0) decides ties exactly: Niblack gives f = t and therefore 255.
 template <int RULE>
-__device__ __forceinline__ uint32_t decide(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
-                                           const RowN &q, float *t_out) {
+__device__ __forceinline__ bool decide(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
+                                       const RowN &q, float *t_out) {
     const double s1d = (double)S1;
     const double D = __builtin_fma(q.nd, (double)S2, -(s1d * s1d));
     const float sq = __builtin_amdgcn_sqrtf((float)D);
-    const uint32_t nfi = q.n * f;  // < 2^24
-    uint32_t g;
+    const uint32_t nfi = __umul24(q.n, f);  // < 2^24
+    bool dark;  // f < t: output 0
     if (RULE == 0) {
         const float lhs = (float)nfi * q.nf;
         const float rhs = (float)S1 * __builtin_fmaf(a.c2, sq, q.c1n);
-        g = lhs < rhs ? 0u : 255u;
+        dark = lhs < rhs;
     } else {
-        g = (float)((int)nfi - (int)S1) < a.k * sq ? 0u : 255u;
+        dark = (float)((int)nfi - (int)S1) < a.k * sq;
     }
     if (t_out) {  // verification only: t itself, Eq. 4 / Niblack in fp32
         const float m = (float)S1 / q.nf;
         const float s = sq / q.nf;
         *t_out = (RULE == 0) ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
     }
-    return g;
+    return dark;
 }
 
 // ---------------------------------------------------------------- output
@@ -329,15 +330,13 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const bool clamp = xr0 < 0 || xr0 + rp + 4 > a.W;
 
     // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1
-    {
-        Stager<C> st;
-        for (int r0 = 0; r0 < win; r0 += RB) {
-            const int nr = min(RB, win - r0);
-            st.fetch(a, base + r0, nr, xr0, clamp);
-            st.store(a, ring, r0, xr0, clamp);
-        }
-    }
     Stager<C> pre;  // rows of the next step, in flight while this one computes
+    pre.init(a);
+    for (int r0 = 0; r0 < win; r0 += RB) {
+        const int nr = min(RB, win - r0);
+        pre.fetch(a, base + r0, nr, xr0, clamp);
+        pre.store(a, ring, r0, nr, xr0, clamp);
+    }
     pre.fetch(a, Y0 + hi, RB, xr0, clamp);
     __syncthreads();
 
@@ -347,6 +346,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const int ib = c - off0 + 1;        // Vb index of column c
     const bool wa = vcol && ia >= 0 && ia < TW;
     const bool wb = vcol && ib >= 0 && ib < vbw;
+    // Columns whose V is not needed in Va / Vb write to a trash slot instead,
+    // which keeps the vertical pass free of branches.
+    uint8_t *trash = (uint8_t *)(Vb2 + RB * vbw);
+    uint16_t *pa1 = wa ? Va1 + ia : (uint16_t *)trash;
+    uint32_t *pa2 = wa ? Va2 + ia : (uint32_t *)(trash + 4);
+    uint16_t *pb1 = wb ? Vb1 + ib : (uint16_t *)(trash + 8);
+    uint32_t *pb2 = wb ? Vb2 + ib : (uint32_t *)(trash + 12);
+    const int sa1 = wa ? TW : 0, sb1 = wb ? vbw : 0;  // row strides (0 keeps trash in place)
     uint32_t v1 = 0, v2 = 0;
     if (vcol) {
         for (int i = 0; i < win; ++i) {
@@ -363,29 +370,30 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
         // Rows of this step go into ring slots that held rows leaving the
         // window in the previous step; no thread reads those any more.
-        pre.store(a, ring, s_in, xr0, clamp);
+        pre.store(a, ring, s_in, RB, xr0, clamp);
         if (y0 + RB < Yend) pre.fetch(a, y0 + RB + hi, RB, xr0, clamp);
         __syncthreads();
 
-        // ---- vertical pass: one LDS column per thread, RB rows
+        // ---- vertical pass: one LDS column per thread, RB rows, no branches
         if (vcol) {
             int se = s_in, sx = (y0 - Y0) % depth;  // entering / leaving row slots
-#pragma unroll 4
+            int fn[RB], fo[RB];
+#pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const int fn = ring[se * rp + c], fo = ring[sx * rp + c];
-                const int d = fn - fo;
-                v1 += (uint32_t)d;
-                v2 += (uint32_t)(d * (fn + fo));
-                if (wa) {
-                    Va1[r * TW + ia] = (uint16_t)v1;
-                    Va2[r * TW + ia] = v2;
-                }
-                if (wb) {
-                    Vb1[r * vbw + ib] = (uint16_t)v1;
-                    Vb2[r * vbw + ib] = v2;
-                }
+                fn[r] = ring[se * rp + c];
+                fo[r] = ring[sx * rp + c];
                 se = (se + 1 == depth) ? 0 : se + 1;
                 sx = (sx + 1 == depth) ? 0 : sx + 1;
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int d = fn[r] - fo[r];
+                v1 += (uint32_t)d;
+                v2 += (uint32_t)(d * (fn[r] + fo[r]));
+                pa1[r * sa1] = (uint16_t)v1;
+                pa2[r * sa1] = v2;
+                pb1[r * sb1] = (uint16_t)v1;
+                pb2[r * sb1] = v2;
             }
         }
         __syncthreads();
@@ -405,9 +413,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         load_u32<OPT>(vb2, B2);
         // starting value: window sum one column left of the tile
         uint32_t h1 = 0, h2 = 0;
-        for (int i = hs; i < win; i += TPR) {
-            h1 += Vb1[hr * vbw + i];
-            h2 += Vb2[hr * vbw + i];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {  // win <= 255 < 8 * 32
+            const int i = hs + it * TPR;
+            if (it * TPR < win) {  // uniform
+                const bool in = i < win;
+                h1 += in ? (uint32_t)Vb1[hr * vbw + i] : 0u;
+                h2 += in ? Vb2[hr * vbw + i] : 0u;
+            }
         }
         // running sums of the entering-minus-leaving columns
         uint32_t E1[OPT], E2[OPT];
@@ -425,7 +438,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const uint32_t b2 = half_total(h2i) + s2i - a2;
 
         // gray levels of the output row (centre of the window)
-        const int fo = ((y - base) % depth) * rp + off0 + lo + hs * OPT;
+        int sy = (y0 - base) % depth + hr;  // ring slot of this output row
+        if (sy >= depth) sy -= depth;
+        const int fo = sy * rp + off0 + lo + hs * OPT;
         const uint32_t fsh = (uint32_t)(fo & 3);
         const uint32_t *fq = (const uint32_t *)(smem + (fo & ~3));
         uint32_t fw[OPT / 4];
@@ -439,22 +454,22 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float tv[OPT];
         if (x_inside) {
-            const RowN q = row_n(a, (uint32_t)(win * ny));
+            const RowN q = row_n(a, (uint32_t)__mul24(win, ny));
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
-                const uint32_t g = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
-                                                STATS ? &tv[j] : nullptr);
-                ow[j >> 2] |= g << (8 * (j & 3));
+                const bool dark = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
+                                               STATS ? &tv[j] : nullptr);
+                ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
             }
         } else {
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int X = xs + j;
                 const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
-                const RowN q = row_n(a, (uint32_t)(nx * ny));
-                const uint32_t g = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
-                                                STATS ? &tv[j] : nullptr);
-                ow[j >> 2] |= g << (8 * (j & 3));
+                const RowN q = row_n(a, (uint32_t)__mul24(nx, ny));
+                const bool dark = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
+                                               STATS ? &tv[j] : nullptr);
+                ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
             }
         }
         if (y < Yend) {
