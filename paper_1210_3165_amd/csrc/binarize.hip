@@ -61,7 +61,7 @@ void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
     const int w = tile_fits(256, win) ? 256 : 128;
     int per_cu = kMaxLds / tile_lds_bytes(w, win);
     if (per_cu < 1) per_cu = 1;
-    if (per_cu > 4) per_cu = 4;  // 4 x 8 waves fill a CU
+    if (per_cu > 8) per_cu = 8;  // 8 x 4 waves fill a CU
     const long target = (long)cus * per_cu;
     const long tiles_x = (W + w - 1) / w;
     long h = (H * tiles_x + target - 1) / target;
@@ -169,6 +169,9 @@ int run(const uint8_t *img, int H, int W, int C, int win, float k, float R, int 
     Plan p;
     rc = make_plan(H, W, win, tile_w, tile_h, &p);
     if (rc) return rc;
+    // Sauvola with k = 0 is t = m, exactly the Niblack rule with k = 0; the
+    // Niblack form decides ties in exact integers.
+    if (rule == BZ_SAUVOLA && k == 0.0f) rule = BZ_NIBLACK;
     PageArgs a;
     fill_args(&a, img, H, W, win, k, R, out, p);
     if (stats) {

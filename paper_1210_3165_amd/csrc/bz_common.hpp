@@ -11,13 +11,13 @@
 
 namespace bz {
 
-// Workgroup shape of the tile kernel: 512 threads (8 wave64s).  The vertical
-// pass gives every thread one LDS column; the horizontal pass gives each of
-// the RB output rows of a step TPR = 32 threads.
-constexpr int kThreads = 512;
-constexpr int kRowsPerStep = 16;                         // RB
+// Workgroup shape of the tile kernel: 256 threads (4 wave64s).  The vertical
+// pass gives every thread two adjacent LDS columns; the horizontal pass gives
+// each of the RB output rows of a step TPR = 32 threads.
+constexpr int kThreads = 256;
+constexpr int kRowsPerStep = 8;                          // RB
 constexpr int kThreadsPerRow = kThreads / kRowsPerStep;  // TPR = 32
-constexpr int kMaxCols = kThreads;                       // LDS columns per tile
+constexpr int kMaxCols = 2 * kThreads;                   // LDS columns per tile
 constexpr int kMaxLds = 160 * 1024;                      // gfx950 LDS per workgroup
 
 // One page as the tile kernel sees it.  All geometry that depends only on the
@@ -45,10 +45,10 @@ struct PageArgs {
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Ring geometry.  rp covers the tile, its halo and up to 16 columns of
-// alignment slack.  depth holds every row one step touches (win + 16) and, when
-// the window reaches less than 16 rows up, enough extra rows that the slots
+// alignment slack.  depth holds every row one step touches (win + RB) and, when
+// the window reaches less than RB rows down, enough extra rows that the slots
 // refilled at the start of a step held no row the previous step still reads
-// as a window centre: depth >= hi + 32.
+// as a window centre: depth >= hi + 2 RB.
 BZ_HD inline int ring_pitch(int tile_w, int win) { return round_up(tile_w + win + 15, 16); }
 BZ_HD inline int ring_depth(int win) {
     const int hi = win - 1 - win / 2;

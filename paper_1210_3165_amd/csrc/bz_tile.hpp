@@ -1,16 +1,16 @@
 // bz_tile.hpp -- gfx950 device code of the exact Sauvola / Niblack tile kernel.
 //
-// One workgroup (512 threads, 8 wave64s) produces a tile of TW output columns
+// One workgroup (256 threads, 4 wave64s) produces a tile of TW output columns
 // by tile_h output rows of one page.  The window statistics of the paper's
 // Sec. 2 (mean and deviation over the full W x W window S) come from exact
 // integer window sums of f and f^2, built separably inside the tile:
 //
 //   ring    LDS ring of gray rows (Sec. 1 Eq. 1 applied while staging), one
-//           row per image row, at least win + 16 rows deep, tile plus halo
+//           row per image row, at least win + 8 rows deep, tile plus halo
 //           wide.  Each
 //           input byte is read from HBM once per tile; the rows of the next
 //           step are loaded into registers while the current step computes.
-//   V pass  one thread per LDS column slides the vertical window down the
+//   V pass  one thread per two LDS columns slides the vertical window down the
 //           tile: V(y) = V(y-1) + f(y+hi) - f(y-lo-1) for V1 = sum f and
 //           V2 = sum f^2 (f_in^2 - f_out^2 formed as (f_in - f_out)(f_in + f_out)).
 //           Each V row is stored twice, shifted so that output column x finds
@@ -122,9 +122,9 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// The job of this thread for a block of up to 16 rows: row i = job / nq of
-// the block, chunk q = job % nq (nq = rp / 16 chunks per row).  rp <= 512
-// gives at most one job per thread.  Rows outside the image load a clamped
+// The job of this thread for a block of up to RB rows: row i = job / nq of
+// the block, chunk q = job % nq (nq = rp / 16 chunks per row).  RB * rp / 16
+// <= 256 gives at most one job per thread.  Rows outside the image load a clamped
 // row (always a valid address) and store zeros.
 template <int C>
 struct Stager {
@@ -186,52 +186,72 @@ __device__ __forceinline__ uint32_t half_total(uint32_t incl) {
 }
 
 // ---------------------------------------------------------------- decision
+//
+// Eq. 3 decides f < t.  With the exact integer window sums S1, S2 and count n,
+// m = S1 / n and s = sqrt(D) / n where D = n S2 - S1^2 is formed exactly in
+// fp64 (every term is an integer below 2^53).
+//
+//   Sauvola (Eq. 4), interior rows (n fixed for the row):
+//       f < t  <=>  f < S1 (c1/n + (c2/n^2) sqrt(D)),  c1 = 1 - k, c2 = k / R
+//   Sauvola, general n:
+//       f < t  <=>  (n f) n < S1 (n c1 + c2 sqrt(D))
+//   Niblack:
+//       f < m + k s  <=>  n f - S1 < k sqrt(D)          (n f, S1 exact integers)
+//
+// Niblack therefore decides ties exactly: a window of constant gray level
+// (D = 0) gives f = t and the output 255.  A Sauvola call with k = 0 is the
+// same rule (t = m) and is routed to the Niblack form by the host.
 
-// Per-row quantities of the decision when n is the same for the whole row
-// segment (n = nx * ny with nx = win inside the image).
-struct RowN {
+// Per-row constants of the interior Sauvola form.
+struct RowSauvola {
     double nd;
-    float nf, c1n;
-    uint32_t n;
+    float c1n, c2n2;
 };
 
-__device__ __forceinline__ RowN row_n(const PageArgs &a, uint32_t n) {
-    RowN q;
-    q.n = n;
+__device__ __forceinline__ RowSauvola row_sauvola(const PageArgs &a, uint32_t n) {
+    RowSauvola q;
     q.nd = (double)n;
-    q.nf = (float)n;
-    q.c1n = a.c1 * q.nf;
+    const float nf = (float)n;
+    q.c1n = a.c1 / nf;
+    q.c2n2 = a.c2 / (nf * nf);
     return q;
 }
 
-// Eq. 3 decision for one pixel from its exact window sums.
-//   Sauvola (Eq. 4): f < m (1 + k (s/R - 1)) with m = S1/n, s = sqrt(D)/n
-//     <=> (n f) n < S1 (n (1 - k) + (k/R) sqrt(D))       (n > 0)
-//   Niblack: f < m + k s  <=>  n f - S1 < k sqrt(D)
-// D = n S2 - S1^2 is formed exactly in fp64 (every term is an integer below
-// 2^53) and n f exactly in integers, so a window of constant gray level
-// (D = 0) decides ties exactly: Niblack gives f = t and therefore 255.
-template <int RULE>
-__device__ __forceinline__ bool decide(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
-                                       const RowN &q, float *t_out) {
+__device__ __forceinline__ float exact_sqrt_d(double nd, uint32_t S1, uint32_t S2) {
     const double s1d = (double)S1;
-    const double D = __builtin_fma(q.nd, (double)S2, -(s1d * s1d));
-    const float sq = __builtin_amdgcn_sqrtf((float)D);
-    const uint32_t nfi = __umul24(q.n, f);  // < 2^24
-    bool dark;  // f < t: output 0
-    if (RULE == 0) {
-        const float lhs = (float)nfi * q.nf;
-        const float rhs = (float)S1 * __builtin_fmaf(a.c2, sq, q.c1n);
-        dark = lhs < rhs;
-    } else {
-        dark = (float)((int)nfi - (int)S1) < a.k * sq;
-    }
-    if (t_out) {  // verification only: t itself, Eq. 4 / Niblack in fp32
-        const float m = (float)S1 / q.nf;
-        const float s = sq / q.nf;
-        *t_out = (RULE == 0) ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
-    }
-    return dark;
+    const double D = __builtin_fma(nd, (double)S2, -(s1d * s1d));
+    return __builtin_amdgcn_sqrtf((float)D);
+}
+
+// t itself (fp32, verification planes only).
+template <int RULE>
+__device__ __forceinline__ float threshold_value(const PageArgs &a, uint32_t S1, uint32_t n, float sq) {
+    const float nf = (float)n;
+    const float m = (float)S1 / nf;
+    const float s = sq / nf;
+    return RULE == 0 ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
+}
+
+// Interior Sauvola: true if f < t (output 0).
+__device__ __forceinline__ bool dark_sauvola_row(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
+                                                 const RowSauvola &q, float &sq) {
+    sq = exact_sqrt_d(q.nd, S1, S2);
+    return (float)f < (float)S1 * __builtin_fmaf(q.c2n2, sq, q.c1n);
+}
+
+// Sauvola, any n.
+__device__ __forceinline__ bool dark_sauvola(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
+                                             uint32_t n, float &sq) {
+    sq = exact_sqrt_d((double)n, S1, S2);
+    const float nf = (float)n;
+    return (float)__umul24(n, f) * nf < (float)S1 * __builtin_fmaf(a.c2, sq, a.c1 * nf);
+}
+
+// Niblack, any n.
+__device__ __forceinline__ bool dark_niblack(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
+                                            uint32_t n, float &sq) {
+    sq = exact_sqrt_d((double)n, S1, S2);
+    return (float)((int)__umul24(n, f) - (int)S1) < a.k * sq;
 }
 
 // ---------------------------------------------------------------- output
@@ -323,6 +343,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     uint16_t *Vb1 = Va1 + RB * TW;
     uint32_t *Va2 = (uint32_t *)(Vb1 + RB * vbw);
     uint32_t *Vb2 = Va2 + RB * TW;
+    uint8_t *trash = (uint8_t *)(Vb2 + RB * vbw);
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
     // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
@@ -340,26 +361,36 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     pre.fetch(a, Y0 + hi, RB, xr0, clamp);
     __syncthreads();
 
-    const int c = tid;  // V-pass column
-    const bool vcol = c < rp;
-    const int ia = c - off0 - win + 1;  // Va index of column c
-    const int ib = c - off0 + 1;        // Vb index of column c
-    const bool wa = vcol && ia >= 0 && ia < TW;
-    const bool wb = vcol && ib >= 0 && ib < vbw;
+    // ---- vertical-pass ownership: LDS columns c0 = 2 tid and c0 + 1
+    const int c0 = 2 * tid;
+    const bool vcol = c0 < rp;
+    // Va index of column c: c - off0 - win + 1; Vb index: c - off0 + 1.
     // Columns whose V is not needed in Va / Vb write to a trash slot instead,
     // which keeps the vertical pass free of branches.
-    uint8_t *trash = (uint8_t *)(Vb2 + RB * vbw);
-    uint16_t *pa1 = wa ? Va1 + ia : (uint16_t *)trash;
-    uint32_t *pa2 = wa ? Va2 + ia : (uint32_t *)(trash + 4);
-    uint16_t *pb1 = wb ? Vb1 + ib : (uint16_t *)(trash + 8);
-    uint32_t *pb2 = wb ? Vb2 + ib : (uint32_t *)(trash + 12);
-    const int sa1 = wa ? TW : 0, sb1 = wb ? vbw : 0;  // row strides (0 keeps trash in place)
-    uint32_t v1 = 0, v2 = 0;
+    uint16_t *pa1[2], *pb1[2];
+    uint32_t *pa2[2], *pb2[2];
+    int sa[2], sb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ia = c0 + h - off0 - win + 1, ib = c0 + h - off0 + 1;
+        const bool wa = vcol && ia >= 0 && ia < TW;
+        const bool wb = vcol && ib >= 0 && ib < vbw;
+        pa1[h] = wa ? Va1 + ia : (uint16_t *)trash;
+        pa2[h] = wa ? Va2 + ia : (uint32_t *)(trash + 4);
+        pb1[h] = wb ? Vb1 + ib : (uint16_t *)(trash + 8);
+        pb2[h] = wb ? Vb2 + ib : (uint32_t *)(trash + 12);
+        sa[h] = wa ? TW : 0;   // row strides (0 keeps trash in place)
+        sb[h] = wb ? vbw : 0;
+    }
+    uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
     if (vcol) {
         for (int i = 0; i < win; ++i) {
-            const uint32_t f = ring[i * rp + c];
-            v1 += f;
-            v2 += f * f;
+            const uint32_t w = *(const uint16_t *)(ring + i * rp + c0);
+            const uint32_t f0 = w & 0xffu, f1 = w >> 8;
+            v1[0] += f0;
+            v2[0] += f0 * f0;
+            v1[1] += f1;
+            v2[1] += f1 * f1;
         }
     }
 
@@ -368,32 +399,36 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
-        // Rows of this step go into ring slots that held rows leaving the
-        // window in the previous step; no thread reads those any more.
+        // Rows of this step go into ring slots whose previous rows no thread
+        // reads any more (see ring_depth).
         pre.store(a, ring, s_in, RB, xr0, clamp);
         if (y0 + RB < Yend) pre.fetch(a, y0 + RB + hi, RB, xr0, clamp);
         __syncthreads();
 
-        // ---- vertical pass: one LDS column per thread, RB rows, no branches
+        // ---- vertical pass: two LDS columns per thread, RB rows, no branches
         if (vcol) {
             int se = s_in, sx = (y0 - Y0) % depth;  // entering / leaving row slots
-            int fn[RB], fo[RB];
+            uint32_t fn[RB], fo[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                fn[r] = ring[se * rp + c];
-                fo[r] = ring[sx * rp + c];
+                fn[r] = *(const uint16_t *)(ring + se * rp + c0);
+                fo[r] = *(const uint16_t *)(ring + sx * rp + c0);
                 se = (se + 1 == depth) ? 0 : se + 1;
                 sx = (sx + 1 == depth) ? 0 : sx + 1;
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const int d = fn[r] - fo[r];
-                v1 += (uint32_t)d;
-                v2 += (uint32_t)(d * (fn[r] + fo[r]));
-                pa1[r * sa1] = (uint16_t)v1;
-                pa2[r * sa1] = v2;
-                pb1[r * sb1] = (uint16_t)v1;
-                pb2[r * sb1] = v2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int en = (int)((fn[r] >> (8 * h)) & 0xffu), lv = (int)((fo[r] >> (8 * h)) & 0xffu);
+                    const int d = en - lv;
+                    v1[h] += (uint32_t)d;
+                    v2[h] += (uint32_t)(d * (en + lv));
+                    pa1[h][r * sa[h]] = (uint16_t)v1[h];
+                    pa2[h][r * sa[h]] = v2[h];
+                    pb1[h][r * sb[h]] = (uint16_t)v1[h];
+                    pb2[h][r * sb[h]] = v2[h];
+                }
             }
         }
         __syncthreads();
@@ -402,15 +437,11 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // Every group runs (rows past the tile compute on stale LDS data and
         // store nothing) so the cross-lane scans see full 32-lane halves.
         const int y = y0 + hr;
-        const uint16_t *va1 = Va1 + hr * TW + hs * OPT;
-        const uint16_t *vb1 = Vb1 + hr * vbw + hs * OPT;
-        const uint32_t *va2 = Va2 + hr * TW + hs * OPT;
-        const uint32_t *vb2 = Vb2 + hr * vbw + hs * OPT;
         uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
-        load_u16<OPT>(va1, A1);
-        load_u16<OPT>(vb1, B1);
-        load_u32<OPT>(va2, A2);
-        load_u32<OPT>(vb2, B2);
+        load_u16<OPT>(Va1 + hr * TW + hs * OPT, A1);
+        load_u16<OPT>(Vb1 + hr * vbw + hs * OPT, B1);
+        load_u32<OPT>(Va2 + hr * TW + hs * OPT, A2);
+        load_u32<OPT>(Vb2 + hr * vbw + hs * OPT, B2);
         // starting value: window sum one column left of the tile
         uint32_t h1 = 0, h2 = 0;
 #pragma unroll
@@ -452,23 +483,22 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         uint32_t ow[OPT / 4];
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
-        float tv[OPT];
-        if (x_inside) {
-            const RowN q = row_n(a, (uint32_t)__mul24(win, ny));
+        float sqv[OPT];
+        if (RULE == 0 && x_inside) {
+            const RowSauvola q = row_sauvola(a, (uint32_t)__mul24(win, ny));
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
-                const bool dark = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
-                                               STATS ? &tv[j] : nullptr);
+                const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
                 ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
             }
         } else {
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int X = xs + j;
-                const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
-                const RowN q = row_n(a, (uint32_t)__mul24(nx, ny));
-                const bool dark = decide<RULE>(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q,
-                                               STATS ? &tv[j] : nullptr);
+                const int nx = x_inside ? win : min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
+                const uint32_t n = (uint32_t)__mul24(nx, ny);
+                const bool dark = RULE == 0 ? dark_sauvola(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j])
+                                            : dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j]);
                 ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
             }
         }
@@ -480,12 +510,12 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                     const int X = xs + j;
                     if (X >= a.W) continue;
                     const size_t i = (size_t)y * a.W + X;
-                    const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
+                    const uint32_t n = (uint32_t)__mul24(min(X + hi, a.W - 1) - max(X - lo, 0) + 1, ny);
                     if (a.gray) a.gray[i] = (uint8_t)byte_at(fw, j);
                     if (a.s1) a.s1[i] = b1 + E1[j];
                     if (a.s2) a.s2[i] = b2 + E2[j];
-                    if (a.n) a.n[i] = (uint32_t)(nx * ny);
-                    if (a.t) a.t[i] = tv[j];
+                    if (a.n) a.n[i] = n;
+                    if (a.t) a.t[i] = threshold_value<RULE>(a, b1 + E1[j], n, sqv[j]);
                 }
             }
         }
