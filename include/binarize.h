@@ -94,7 +94,7 @@ int binarize_async(const uint8_t *img, int H, int W_img, int channels, int win,
 /*
  * binarize_tuned -- as binarize_async with an explicit tile shape: tile_w
  * output columns (128 or 256; 256 needs win <= 241) by tile_h output rows
- * (a multiple of 16, 16..4096) per workgroup.  The result is bit-identical
+ * (a multiple of 8, 8..4096) per workgroup.  The result is bit-identical
  * for every tile shape; only the speed changes.  BZ_ERR_TILE otherwise.
  */
 int binarize_tuned(const uint8_t *img, int H, int W_img, int channels, int win,
