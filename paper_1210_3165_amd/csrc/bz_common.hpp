@@ -60,12 +60,19 @@ BZ_HD inline int ring_bytes(int tile_w, int win) {
 // Width of the Vb rows: the tile, or the whole first window if that is wider.
 BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
 // LDS layout: ring | Va1 [RB][TW] u16 | Vb1 [RB][vbw] u16 | Va2 [RB][TW] u32 |
-// Vb2 [RB][vbw] u32 | 16-byte trash slot (target of writes that fall outside
-// Va / Vb, so the vertical pass needs no branches)
+// Vb2 [RB][vbw] u32 | trash [4][kThreads] u32 (per-thread targets of the writes
+// that fall outside Va / Vb, so the vertical pass needs no branches and no two
+// lanes write the same address)
 BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
     const int w = vb_width(tile_w, win);
-    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4) + 16;
+    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4) + kThreads * 16;
 }
+
+// Position of entry x in a V2 row of `width` entries.  Thread h of a row group
+// reads entries 8h .. 8h+7 as two 16-byte quads; quads 8h..8h+3 of all threads
+// are packed first and quads 8h+4..8h+7 after width/2, so each 128-bit read of
+// a wave covers consecutive addresses.
+BZ_HD inline int v2_pos(int x, int width) { return ((x >> 3) << 2) + (x & 3) + (((x >> 2) & 1) ? width / 2 : 0); }
 
 // Does this tile configuration fit the hardware?
 inline bool tile_fits(int tile_w, int win) {

@@ -310,11 +310,13 @@ __device__ __forceinline__ void load_u16(const uint16_t *p, uint32_t (&v)[OPT]) 
     }
 }
 
+// Entries OPT*h .. OPT*h+OPT-1 of a V2 row laid out by v2_pos.
 template <int OPT>
-__device__ __forceinline__ void load_u32(const uint32_t *p, uint32_t (&v)[OPT]) {
+__device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, uint32_t (&v)[OPT]) {
 #pragma unroll
     for (int i = 0; i < OPT / 4; ++i) {
-        const uint4 q = *(const uint4 *)(p + 4 * i);
+        const int x = OPT * h + 4 * i;
+        const uint4 q = *(const uint4 *)(row + v2_pos(x, width));
         v[4 * i] = q.x;
         v[4 * i + 1] = q.y;
         v[4 * i + 2] = q.z;
@@ -343,7 +345,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     uint16_t *Vb1 = Va1 + RB * TW;
     uint32_t *Va2 = (uint32_t *)(Vb1 + RB * vbw);
     uint32_t *Vb2 = Va2 + RB * TW;
-    uint8_t *trash = (uint8_t *)(Vb2 + RB * vbw);
+    // per-thread trash words, field-major ([4][kThreads] u32) so that the
+    // lanes of a wave write consecutive banks
+    uint32_t *trash = Vb2 + RB * vbw + tid;
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
     // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
@@ -375,10 +379,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const int ia = c0 + h - off0 - win + 1, ib = c0 + h - off0 + 1;
         const bool wa = vcol && ia >= 0 && ia < TW;
         const bool wb = vcol && ib >= 0 && ib < vbw;
-        pa1[h] = wa ? Va1 + ia : (uint16_t *)trash;
-        pa2[h] = wa ? Va2 + ia : (uint32_t *)(trash + 4);
-        pb1[h] = wb ? Vb1 + ib : (uint16_t *)(trash + 8);
-        pb2[h] = wb ? Vb2 + ib : (uint32_t *)(trash + 12);
+        pa1[h] = wa ? Va1 + ia : (uint16_t *)(trash) + h;
+        pa2[h] = wa ? Va2 + v2_pos(ia, TW) : trash + kThreads;
+        pb1[h] = wb ? Vb1 + ib : (uint16_t *)(trash + 2 * kThreads) + h;
+        pb2[h] = wb ? Vb2 + v2_pos(ib, vbw) : trash + 3 * kThreads;
         sa[h] = wa ? TW : 0;   // row strides (0 keeps trash in place)
         sb[h] = wb ? vbw : 0;
     }
@@ -440,17 +444,20 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
         load_u16<OPT>(Va1 + hr * TW + hs * OPT, A1);
         load_u16<OPT>(Vb1 + hr * vbw + hs * OPT, B1);
-        load_u32<OPT>(Va2 + hr * TW + hs * OPT, A2);
-        load_u32<OPT>(Vb2 + hr * vbw + hs * OPT, B2);
-        // starting value: window sum one column left of the tile
+        load_v2<OPT>(Va2 + hr * TW, TW, hs, A2);
+        load_v2<OPT>(Vb2 + hr * vbw, vbw, hs, B2);
+        // starting value: window sum one column left of the tile.  Every read
+        // stays inside the LDS allocation (rows are vbw >= 32 * ceil(win / 32)
+        // wide, and the last Vb2 row is followed by the trash slot and the
+        // ring of the next row); entries at i >= win are masked after the read.
         uint32_t h1 = 0, h2 = 0;
 #pragma unroll
         for (int it = 0; it < 8; ++it) {  // win <= 255 < 8 * 32
-            const int i = hs + it * TPR;
-            if (it * TPR < win) {  // uniform
-                const bool in = i < win;
-                h1 += in ? (uint32_t)Vb1[hr * vbw + i] : 0u;
-                h2 += in ? Vb2[hr * vbw + i] : 0u;
+            if (it * TPR < win) {         // uniform
+                const int i = hs + it * TPR;
+                const uint32_t x1 = Vb1[hr * vbw + i], x2 = Vb2[hr * vbw + v2_pos(i, vbw)];
+                h1 += i < win ? x1 : 0u;
+                h2 += i < win ? x2 : 0u;
             }
         }
         // running sums of the entering-minus-leaving columns
@@ -484,18 +491,30 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float sqv[OPT];
-        if (RULE == 0 && x_inside) {
-            const RowSauvola q = row_sauvola(a, (uint32_t)__mul24(win, ny));
+        if (x_inside) {  // n = win * ny for the whole row segment
+            const uint32_t n = (uint32_t)__mul24(win, ny);
+            if (RULE == 0) {
+                const RowSauvola q = row_sauvola(a, n);
 #pragma unroll
-            for (int j = 0; j < OPT; ++j) {
-                const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
-                ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                for (int j = 0; j < OPT; ++j) {
+                    const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
+                    ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                }
+            } else {
+                const double nd = (double)n;
+#pragma unroll
+                for (int j = 0; j < OPT; ++j) {
+                    const uint32_t S1 = b1 + E1[j];
+                    sqv[j] = exact_sqrt_d(nd, S1, b2 + E2[j]);
+                    const bool dark = (float)((int)__umul24(n, byte_at(fw, j)) - (int)S1) < a.k * sqv[j];
+                    ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                }
             }
         } else {
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int X = xs + j;
-                const int nx = x_inside ? win : min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
+                const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
                 const uint32_t n = (uint32_t)__mul24(nx, ny);
                 const bool dark = RULE == 0 ? dark_sauvola(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j])
                                             : dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j]);
