@@ -85,12 +85,12 @@ def run_cpu_baseline(img: np.ndarray, budget_s: float) -> dict:
     # grow a probe sample until it takes a measurable time, then size the
     # final sample to the budget
     n = 256
-    while n < 2_000_000:
+    while n < 16_000_000:
         dt = timed(n)
         if dt > 0.1 * budget_s:
             break
         n *= 4
-    n = int(min(2_000_000, max(256, n * budget_s / max(dt, 1e-6))))
+    n = int(min(16_000_000, max(256, n * budget_s / max(dt, 1e-6))))
     ys = rng.integers(0, H, n).astype(np.int32)
     xs = rng.integers(0, W, n).astype(np.int32)
     t0 = time.perf_counter()
@@ -115,7 +115,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--pool-mb", type=int, default=1024, help="rotating buffer pool size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
     args = ap.parse_args()
 
