@@ -120,8 +120,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(pages are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the binarizer has no multi-GPU path "
+              "(pages are independent and need no collective)", file=sys.stderr)
         return 2
 
     import torch
