@@ -108,6 +108,78 @@ def run_cpu_baseline(img: np.ndarray, budget_s: float) -> dict:
     }
 
 
+def batch_jobs(name: str, dev):
+    """Device-resident pages of the batched workloads.
+
+    batch-rgb:   64 RGB A4 pages (3508 x 2480), Sauvola win 31, k 0.34, R 128;
+                 4 distinct generated pages, each placed in 16 buffers.
+    batch-mixed: 512 gray pages, H, W ~ U{300..4000}, win from
+                 {15, 31, 61, 101, 151}, k ~ U[0.2, 0.5], R 128; page contents
+                 are crops of one generated 4000 x 4000 page.
+    """
+    import torch
+
+    import pagegen
+    jobs = []
+    if name == "batch-rgb":
+        pages = pagegen.config2(n_pages=4)
+        for i in range(64):
+            p = pages[i % 4]
+            img = torch.from_numpy(p.img).to(dev)
+            jobs.append((img, torch.empty(p.img.shape[:2], dtype=torch.uint8, device=dev), p.win,
+                         _f32(p.k), 128.0, 0))
+    elif name == "batch-mixed":
+        big = pagegen.page(4000, 4000, pagegen.strokes_for(4000, 4000), seed=3000)
+        rng = np.random.default_rng(7)
+        for (H, W, win, k) in pagegen.config3_specs(512):
+            y0 = int(rng.integers(0, 4001 - H))
+            x0 = int(rng.integers(0, 4001 - W))
+            img = torch.from_numpy(np.ascontiguousarray(big[y0:y0 + H, x0:x0 + W])).to(dev)
+            jobs.append((img, torch.empty((H, W), dtype=torch.uint8, device=dev), win, k, 128.0, 0))
+    else:
+        raise ValueError(name)
+    return jobs
+
+
+def run_batch_workload(name: str, reps: int) -> dict:
+    """Per-image launches vs one persistent launch (direct and graph replay)
+    on the same device-resident pages; outputs checked identical."""
+    import torch
+
+    import paper_1210_3165_amd as bz
+    dev = torch.device("cuda:0")
+    jobs = batch_jobs(name, dev)
+    px = sum(j[1].numel() for j in jobs)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def per_image():
+        for img, out, win, k, R, rule in jobs:
+            bz.binarize(img, win, k, R, rule, out=out)
+
+    ms_single = timed(per_image)
+    ref = [j[1].clone() for j in jobs]
+    res = {"workload": name, "pages": len(jobs), "pixels": px,
+           "per_image": {"ms": ms_single, "gpix_s": px / ms_single / 1e6}}
+    with bz.Batch(len(jobs)) as B:
+        for mode, graph in (("batch_direct", False), ("batch_graph", True)):
+            ms = timed(lambda: B.run(jobs, use_graph=graph))
+            same = all(torch.equal(r, j[1]) for r, j in zip(ref, jobs))
+            res[mode] = {"ms": ms, "gpix_s": px / ms / 1e6, "identical_to_per_image": same}
+        res["batch_grid"] = B.info()["grid"]
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +189,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--workload", default="page4096",
+                    choices=["page4096", "batch-rgb", "batch-mixed"],
+                    help="page4096: the metric line; batch-*: per-image vs persistent batch")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -135,6 +210,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     bz.lib()
+    if args.workload != "page4096":
+        print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20))), flush=True)
+        return 0
 
     S = args.size
     page = pagegen.config1(size=S)[0].img

@@ -113,6 +113,46 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
                    uint8_t *gray, uint32_t *s1, uint32_t *s2, uint32_t *n,
                    float *t, void *stream);
 
+/*
+ * Batched form: many pages of uneven size, channels, window, k, R and rule in
+ * ONE persistent launch.  Every tile of every page is a work item that
+ * workgroups take from a device counter, so uneven pages leave no idle tail
+ * per page; each page's output is bit-identical to binarizing it alone.
+ *
+ * binarize_batch_create -- allocate a batch object for up to max_pages pages:
+ *   a device page table, a pinned host staging copy of it, a work counter,
+ *   a capture stream and an event.  lds_cap_bytes bounds the LDS of one
+ *   workgroup (0: 80 KiB, i.e. 2 workgroups per CU); pages whose window
+ *   needs more fail with BZ_ERR_TILE.  The only entry points that allocate.
+ * binarize_batch_run -- plan the pages (host, into the pinned table), then
+ *   enqueue on `stream`: table copy, counter reset, persistent kernel.  With
+ *   use_graph != 0 the three are captured into a HIP graph on the first call
+ *   and replayed afterwards (the table contents change, the graph does not).
+ *   Waits for the previous run of the same object before rewriting its
+ *   table.  Every img/out pointer must stay valid until the stream reaches
+ *   the end of the run.  Errors as for binarize (per page), BZ_ERR_SHAPE for
+ *   n_pages outside [1, max_pages].
+ * binarize_batch_info -- persistent grid size, LDS cap, items of last run.
+ * binarize_batch_destroy -- wait for the last run, free everything.
+ */
+typedef struct bz_page {
+    const uint8_t *img; /* device, H x W_img x channels                     */
+    uint8_t *out;       /* device, H x W_img                                */
+    int H, W_img, channels, win;
+    float k, R;
+    int rule;           /* BZ_SAUVOLA or BZ_NIBLACK                         */
+    int tile_w, tile_h; /* 0: chosen by the library (tile_h default 128)   */
+} bz_page;
+
+typedef struct binarize_batch binarize_batch;
+
+int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out);
+int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages,
+                       int use_graph, void *stream);
+int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap,
+                        int *last_items);
+void binarize_batch_destroy(binarize_batch *b);
+
 /* Default tile shape binarize/binarize_async pick for a problem. */
 int binarize_default_tile(int H, int W_img, int channels, int win,
                           int *tile_w, int *tile_h);

@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
-    "default_tile", "library_path", "lib",
+    "default_tile", "library_path", "lib", "Batch",
 ]
 
 SAUVOLA = 0
@@ -163,3 +163,99 @@ def default_tile(H: int, W: int, channels: int, win: int) -> tuple[int, int]:
     if rc:
         raise BinarizeError(rc, "binarize_default_tile")
     return tw.value, th.value
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent launch
+# ---------------------------------------------------------------------------
+
+class _Page(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("H", ctypes.c_int), ("W_img", ctypes.c_int), ("channels", ctypes.c_int),
+                ("win", ctypes.c_int), ("k", ctypes.c_float), ("R", ctypes.c_float),
+                ("rule", ctypes.c_int), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int)]
+
+
+def _batch_lib() -> ctypes.CDLL:
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        L.binarize_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+        L.binarize_batch_create.restype = ctypes.c_int
+        L.binarize_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Page), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p]
+        L.binarize_batch_run.restype = ctypes.c_int
+        L.binarize_batch_info.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 3
+        L.binarize_batch_info.restype = ctypes.c_int
+        L.binarize_batch_destroy.argtypes = [ctypes.c_void_p]
+        L.binarize_batch_destroy.restype = None
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many pages in one persistent launch (``binarize_batch_*`` in the C ABI).
+
+    ``run(jobs)`` takes a list of ``(img, out, win, k, R, rule)`` or
+    ``(img, out, win, k, R, rule, (tile_w, tile_h))`` tuples of CUDA tensors
+    and enqueues the whole batch on the current stream; with
+    ``use_graph=True`` the launch sequence is a replayed HIP graph.  The
+    tensors must stay alive until the stream has finished the batch.
+    """
+
+    def __init__(self, max_pages: int, lds_cap: int = 0, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        L = _batch_lib()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = L.binarize_batch_create(int(max_pages), int(lds_cap), ctypes.byref(h))
+        if rc:
+            raise BinarizeError(rc, "binarize_batch_create")
+        self._h = h
+        self.max_pages = int(max_pages)
+        self._keep = None
+
+    def run(self, jobs, use_graph: bool = True, stream: torch.cuda.Stream | None = None) -> None:
+        if self._h is None:
+            raise RuntimeError("batch is closed")
+        n = len(jobs)
+        arr = (_Page * max(n, 1))()
+        for i, job in enumerate(jobs):
+            img, out, win, k, R, rule = job[:6]
+            tile = job[6] if len(job) > 6 and job[6] is not None else (0, 0)
+            H, W, C = _check_image(img)
+            if out.shape != (H, W) or out.dtype != torch.uint8 or not out.is_contiguous() \
+                    or out.device != img.device:
+                raise ValueError(f"page {i}: out must be a contiguous HxW uint8 tensor on the image's device")
+            arr[i] = _Page(img.data_ptr(), out.data_ptr(), H, W, C, int(win), float(k), float(R),
+                           _rule(rule), int(tile[0]), int(tile[1]))
+        with torch.cuda.device(self.device):
+            s = ctypes.c_void_p(_stream_ptr(stream, self.device))
+            rc = _batch_lib().binarize_batch_run(self._h, arr, n, 1 if use_graph else 0, s)
+        if rc:
+            raise BinarizeError(rc, "binarize_batch_run")
+        self._keep = jobs  # the tensors must outlive the enqueued work
+
+    def info(self) -> dict:
+        g, l, it = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = _batch_lib().binarize_batch_info(self._h, ctypes.byref(g), ctypes.byref(l), ctypes.byref(it))
+        if rc:
+            raise BinarizeError(rc, "binarize_batch_info")
+        return {"grid": g.value, "lds_cap": l.value, "last_items": it.value}
+
+    def close(self) -> None:
+        if self._h is not None:
+            _batch_lib().binarize_batch_destroy(self._h)
+            self._h = None
+            self._keep = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

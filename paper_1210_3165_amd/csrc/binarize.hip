@@ -13,8 +13,12 @@
 using namespace bz;
 
 namespace {
-
 thread_local int t_last_hip = 0;
+}  // namespace
+
+void bz::set_last_hip_error(int e) { t_last_hip = e; }
+
+namespace {
 
 int hip_fail(hipError_t e) {
     t_last_hip = (int)e;

@@ -1,0 +1,358 @@
+// bz_batch.hip -- many pages of uneven size, channels, window and rule in
+// one persistent launch (the batched form of the tile kernel), optionally
+// replayed from a captured HIP graph.
+//
+// Every tile of every page is one work item.  Items are numbered page by page
+// (page p owns items [item0[p], item0[p] + tiles[p])); a workgroup takes the
+// next item from a device counter, finds its page by binary search over
+// item0, and runs the same tile code as the single-page kernel.  Results are
+// bit-identical to binarizing each page alone: the arithmetic of a pixel does
+// not depend on which tile, launch or neighbour page it is computed with.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "binarize.h"
+#include "bz_common.hpp"
+#include "bz_tile.hpp"
+
+using namespace bz;
+
+namespace {
+
+constexpr int kKinds = 8;  // (tile_w == 256) * 4 + (channels == 3) * 2 + rule
+
+// Table header: one item list per tile variant.  Pages of one kind are
+// contiguous in the page array, starting at page0[kind].
+struct BatchHeader {
+    uint32_t n_pages[kKinds];
+    uint32_t n_items[kKinds];
+    uint32_t page0[kKinds];
+    uint32_t pad[8];
+};
+
+struct BatchPage {
+    PageArgs a;
+    int item0;  // first work item of this page within its kind
+    int pad[3];
+};
+
+// Persistent workgroups of one tile variant pull items of that variant until
+// its counter passes n_items; every workgroup reaches that exit because the
+// counter only grows.
+template <int KIND>
+__global__ void __launch_bounds__(kThreads, 2)
+    bz_batch_kernel(const BatchHeader *__restrict__ hdr, const BatchPage *__restrict__ all_pages,
+                    uint32_t *__restrict__ counters) {
+    constexpr int TW = (KIND & 4) ? 256 : 128;
+    constexpr int C = (KIND & 2) ? 3 : 1;
+    constexpr int RULE = KIND & 1;
+    extern __shared__ uint4 bz_lds[];
+    __shared__ int s_item;
+    const int n_items = (int)hdr->n_items[KIND];
+    const int n_pages = (int)hdr->n_pages[KIND];
+    const BatchPage *pages = all_pages + hdr->page0[KIND];
+    uint32_t *counter = counters + KIND;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        // uniform across the workgroup: keep it (and the page search and page
+        // fields that follow) in scalar registers
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();  // every thread has read s_item before it is rewritten
+        if (item >= n_items) break;
+        int lo = 0, hi = n_pages - 1;
+        while (lo < hi) {  // last page whose first item is <= item
+            const int mid = (lo + hi + 1) >> 1;
+            if (pages[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        process_tile<TW, C, RULE, false>(pages[lo].a, item - pages[lo].item0, (uint8_t *)bz_lds);
+        __syncthreads();  // the next item restages LDS
+    }
+}
+
+using BatchKernel = void (*)(const BatchHeader *, const BatchPage *, uint32_t *);
+const BatchKernel kBatchKernels[kKinds] = {
+    bz_batch_kernel<0>, bz_batch_kernel<1>, bz_batch_kernel<2>, bz_batch_kernel<3>,
+    bz_batch_kernel<4>, bz_batch_kernel<5>, bz_batch_kernel<6>, bz_batch_kernel<7>,
+};
+
+__global__ void bz_counter_reset(uint32_t *counters) {
+    if (threadIdx.x < kKinds) counters[threadIdx.x] = 0u;
+}
+
+int fail(hipError_t e) {
+    bz::set_last_hip_error((int)e);
+    return BZ_ERR_HIP;
+}
+
+}  // namespace
+
+// Opaque batch object (binarize_batch in the C ABI).
+struct binarize_batch {
+    int max_pages;
+    int lds_cap;
+    int grid;
+    size_t table_bytes;
+    void *host_table;    // pinned staging copy of header + pages
+    void *dev_table;     // device copy read by the kernel
+    uint32_t *counter;   // device work counter
+    hipStream_t cap_stream;
+    hipGraph_t graph;       // captured for the set of kinds in graph_mask
+    hipGraphExec_t exec;
+    int graph_mask;
+    int kind_mask;          // kinds present in the last planned batch
+    hipEvent_t done;     // completion of the last run (guards the pinned table)
+    bool pending;
+    int last_items;
+};
+
+namespace {
+
+// Validation shared with the single-page path (same rules, same codes).
+int check_page(const bz_page &p) {
+    if (!p.img || !p.out) return BZ_ERR_NULL;
+    if (p.H < 1 || p.W_img < 1) return BZ_ERR_SHAPE;
+    if (p.channels != 1 && p.channels != 3) return BZ_ERR_CHANNELS;
+    if ((int64_t)p.H * p.W_img * p.channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
+    if (p.win < 1 || p.win > 255) return BZ_ERR_WINDOW;
+    if (p.rule != BZ_SAUVOLA && p.rule != BZ_NIBLACK) return BZ_ERR_RULE;
+    if (!std::isfinite(p.k) || !std::isfinite(p.R) || !(p.R > 0.0f)) return BZ_ERR_PARAM;
+    const uintptr_t i0 = (uintptr_t)p.img, o0 = (uintptr_t)p.out;
+    const size_t ni = (size_t)p.H * p.W_img * p.channels, no = (size_t)p.H * p.W_img;
+    if (o0 < i0 + ni && i0 < o0 + no) return BZ_ERR_ALIAS;
+    return BZ_OK;
+}
+
+// Tile for one page within the batch's LDS cap: the caller's choice if it
+// fits, else 256 columns when the window allows, else 128; tile_h 128 unless
+// given.
+int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
+    int w = p.tile_w, h = p.tile_h;
+    if (w == 0) {
+        w = (tile_fits(256, p.win) && tile_lds_bytes(256, p.win) <= lds_cap) ? 256 : 128;
+    }
+    if (h == 0) h = 128;
+    if (w != 128 && w != 256) return BZ_ERR_TILE;
+    if (h < kRowsPerStep || h > 4096 || h % kRowsPerStep) return BZ_ERR_TILE;
+    if (!tile_fits(w, p.win) || tile_lds_bytes(w, p.win) > lds_cap) return BZ_ERR_TILE;
+    *tw = w;
+    *th = h;
+    return BZ_OK;
+}
+
+// Fill header + pages of the table at `mem`, pages grouped by tile variant;
+// returns the total item count in *items and the kinds present in *mask.
+int plan(const bz_page *pages, int n, int lds_cap, void *mem, int *items, int *mask) {
+    BatchHeader *hdr = (BatchHeader *)mem;
+    BatchPage *bp = (BatchPage *)(hdr + 1);
+    std::memset(hdr, 0, sizeof(*hdr));
+    // pass 1: validate, choose tiles, count pages per kind
+    int kinds[kKinds] = {0};
+    for (int i = 0; i < n; ++i) {
+        const bz_page &p = pages[i];
+        int rc = check_page(p);
+        if (rc) return rc;
+        int tw, th;
+        rc = page_tile(p, lds_cap, &tw, &th);
+        if (rc) return rc;
+        const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;  // t = m either way
+        kinds[(tw == 256) * 4 + (p.channels == 3) * 2 + rule]++;
+    }
+    int start[kKinds], fill[kKinds];
+    for (int q = 0, acc = 0; q < kKinds; ++q) {
+        start[q] = fill[q] = acc;
+        hdr->page0[q] = (uint32_t)acc;
+        hdr->n_pages[q] = (uint32_t)kinds[q];
+        acc += kinds[q];
+    }
+    // pass 2: fill, page order kept within a kind
+    long total = 0;
+    long per_kind[kKinds] = {0};
+    *mask = 0;
+    for (int i = 0; i < n; ++i) {
+        const bz_page &p = pages[i];
+        int tw, th;
+        page_tile(p, lds_cap, &tw, &th);
+        const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;
+        const int q = (tw == 256) * 4 + (p.channels == 3) * 2 + rule;
+        BatchPage &e = bp[fill[q]++];
+        PageArgs &a = e.a;
+        std::memset(&e, 0, sizeof(e));
+        a.img = p.img;
+        a.out = p.out;
+        a.H = p.H;
+        a.W = p.W_img;
+        a.win = p.win;
+        a.lo = p.win / 2;
+        a.hi = p.win - 1 - a.lo;
+        a.k = p.k;
+        a.c1 = (float)(1.0 - (double)p.k);
+        a.c2 = (float)((double)p.k / (double)p.R);
+        a.tile_h = th;
+        a.tiles_x = (p.W_img + tw - 1) / tw;
+        a.n_tiles = a.tiles_x * ((p.H + th - 1) / th);
+        a.rp = ring_pitch(tw, p.win);
+        a.depth = ring_depth(p.win);
+        e.item0 = (int)per_kind[q];
+        per_kind[q] += a.n_tiles;
+        total += a.n_tiles;
+        if (per_kind[q] >= (1L << 31)) return BZ_ERR_SHAPE;
+        *mask |= 1 << q;
+    }
+    (void)start;
+    for (int q = 0; q < kKinds; ++q) hdr->n_items[q] = (uint32_t)per_kind[q];
+    *items = (int)(total < (1L << 31) ? total : (1L << 31) - 1);
+    return BZ_OK;
+}
+
+// Enqueue table copy, counter reset and one persistent kernel per kind in
+// `mask` (kinds run one after another on the stream).
+int record(binarize_batch *b, int mask, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(b->dev_table, b->host_table, b->table_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(e);
+    hipLaunchKernelGGL(bz_counter_reset, dim3(1), dim3(64), 0, st, b->counter);
+    const BatchHeader *hdr = (const BatchHeader *)b->dev_table;
+    const BatchPage *pg = (const BatchPage *)(hdr + 1);
+    for (int q = 0; q < kKinds; ++q) {
+        if (!(mask & (1 << q))) continue;
+        hipLaunchKernelGGL(kBatchKernels[q], dim3((unsigned)b->grid), dim3(kThreads), (unsigned)b->lds_cap, st, hdr,
+                           pg, b->counter);
+    }
+    e = hipGetLastError();
+    return e == hipSuccess ? BZ_OK : fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out) {
+    if (!out) return BZ_ERR_NULL;
+    *out = nullptr;
+    if (max_pages < 1 || max_pages > (1 << 20)) return BZ_ERR_SHAPE;
+    if (lds_cap_bytes <= 0) lds_cap_bytes = 80 * 1024;
+    // room for the item counter word kept in static LDS
+    if (lds_cap_bytes < tile_lds_bytes(128, 1) || lds_cap_bytes > kMaxLds - 64) return BZ_ERR_TILE;
+    binarize_batch *b = new (std::nothrow) binarize_batch();
+    if (!b) return BZ_ERR_HIP;
+    b->max_pages = max_pages;
+    b->lds_cap = lds_cap_bytes;
+    b->table_bytes = sizeof(BatchHeader) + (size_t)max_pages * sizeof(BatchPage);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < kKinds; ++q)
+        (void)hipFuncSetAttribute((const void *)kBatchKernels[q], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kMaxLds - 64);
+    (void)hipGetLastError();
+    int per_cu = 1 << 30, dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+        delete b;
+        return fail(e);
+    }
+    for (int q = 0; q < kKinds; ++q) {  // the grid that fills the GPU for every kind
+        int pc = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kBatchKernels[q], kThreads, lds_cap_bytes)) !=
+            hipSuccess) {
+            delete b;
+            return fail(e);
+        }
+        if (pc < per_cu) per_cu = pc;
+    }
+    if (per_cu < 1) {
+        delete b;
+        return BZ_ERR_TILE;
+    }
+    b->grid = cus * per_cu;
+    if ((e = hipHostMalloc(&b->host_table, b->table_bytes, hipHostMallocDefault)) != hipSuccess) {
+        delete b;
+        return fail(e);
+    }
+    if ((e = hipMalloc(&b->dev_table, b->table_bytes)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->counter, kKinds * sizeof(uint32_t))) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
+        binarize_batch_destroy(b);
+        return fail(e);
+    }
+    std::memset(b->host_table, 0, b->table_bytes);
+    *out = b;
+    return BZ_OK;
+}
+
+int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages, int use_graph, void *stream) {
+    if (!b || !pages) return BZ_ERR_NULL;
+    if (n_pages < 1 || n_pages > b->max_pages) return BZ_ERR_SHAPE;
+    hipStream_t st = (hipStream_t)stream;
+    // the pinned table may still be read by the previous run's copy
+    if (b->pending) {
+        hipError_t e = hipEventSynchronize(b->done);
+        if (e != hipSuccess) return fail(e);
+        b->pending = false;
+    }
+    int items = 0, mask = 0;
+    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, &items, &mask);
+    if (rc) return rc;
+    b->last_items = items;
+    b->kind_mask = mask;
+    if (use_graph) {
+        if (b->exec && b->graph_mask != mask) {  // a different set of kinds: capture again
+            (void)hipGraphExecDestroy(b->exec);
+            (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+        }
+        if (!b->exec) {
+            hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return fail(e);
+            rc = record(b, mask, b->cap_stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->cap_stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(e);
+            b->graph = g;
+            if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return fail(e);
+            b->graph_mask = mask;
+        }
+        hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) return fail(e);
+    } else {
+        rc = record(b, mask, st);
+        if (rc) return rc;
+    }
+    hipError_t e = hipEventRecord(b->done, st);
+    if (e != hipSuccess) return fail(e);
+    b->pending = true;
+    return BZ_OK;
+}
+
+int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap, int *last_items) {
+    if (!b) return BZ_ERR_NULL;
+    if (grid) *grid = b->grid;
+    if (lds_cap) *lds_cap = b->lds_cap;
+    if (last_items) *last_items = b->last_items;
+    return BZ_OK;
+}
+
+void binarize_batch_destroy(binarize_batch *b) {
+    if (!b) return;
+    if (b->pending) (void)hipEventSynchronize(b->done);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->counter) (void)hipFree(b->counter);
+    if (b->dev_table) (void)hipFree(b->dev_table);
+    if (b->host_table) (void)hipHostFree(b->host_table);
+    delete b;
+}
+
+
+}  // extern "C"

@@ -74,6 +74,10 @@ BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
 // a wave covers consecutive addresses.
 BZ_HD inline int v2_pos(int x, int width) { return ((x >> 3) << 2) + (x & 3) + (((x >> 2) & 1) ? width / 2 : 0); }
 
+// HIP error of the last failed runtime call on this thread (kept by the
+// single-page entry points and the batch entry points alike).
+void set_last_hip_error(int e);
+
 // Does this tile configuration fit the hardware?
 inline bool tile_fits(int tile_w, int win) {
     if (tile_w != 128 && tile_w != 256) return false;

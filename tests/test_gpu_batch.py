@@ -1,0 +1,118 @@
+"""GPU: the batched persistent launch (and its graph replay) gives every page
+exactly the bytes the single-page entry point gives it, and those agree
+with the oracle."""
+import numpy as np
+import pytest
+
+from conftest import f32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_3165_amd as m
+    m.lib()
+    return m
+
+
+def mixed_jobs(seed, n, max_side=700):
+    """Uneven pages: gray and RGB, Sauvola and Niblack (k = 0 included),
+    windows 1..151 (odd and even), ragged sizes down to 1x1."""
+    import pagegen
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(n):
+        H, W = int(rng.integers(1, max_side)), int(rng.integers(1, max_side))
+        if i == 0:
+            H, W = 1, 1
+        C = int(rng.choice([1, 3]))
+        win = int(rng.choice([1, 2, 15, 16, 31, 61, 101, 151]))
+        rule = int(rng.integers(0, 2))
+        k = 0.0 if i % 7 == 3 else f32(float(rng.uniform(-0.3, 0.6)))
+        img = pagegen.page(H, W, max(1, pagegen.strokes_for(H, W)), seed=seed * 1000 + i, channels=C)
+        jobs.append((img, win, k, 128.0, rule))
+    return jobs
+
+
+def run_batch(bz, B, jobs, use_graph):
+    dev = []
+    for img, win, k, R, rule in jobs:
+        t = torch.from_numpy(img).cuda()
+        o = torch.full(img.shape[:2], 7, dtype=torch.uint8, device="cuda")
+        dev.append((t, o, win, k, R, rule))
+    B.run(dev, use_graph=use_graph)
+    torch.cuda.synchronize()
+    return [d[1].cpu().numpy() for d in dev]
+
+
+def single(bz, img, win, k, R, rule):
+    out = bz.binarize(torch.from_numpy(img).cuda(), win, k, R, rule)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_single_pages(bz, oracle_mod, use_graph):
+    from oracle.compare import compare_out
+    jobs = mixed_jobs(11, 24)
+    with bz.Batch(64) as B:
+        outs = run_batch(bz, B, jobs, use_graph)
+        info = B.info()
+    assert info["grid"] > 0 and info["last_items"] > len(jobs) - 1
+    for (img, win, k, R, rule), out in zip(jobs, outs):
+        assert np.array_equal(out, single(bz, img, win, k, R, rule)), (img.shape, win, rule)
+        if img.shape[0] * img.shape[1] * min(win, img.shape[0]) * min(win, img.shape[1]) < 3e8:
+            ref = oracle_mod.binarize(img, win, k, R, rule)
+            assert compare_out(out, ref.out, ref.gray, ref.t)["ok"]
+
+
+def test_graph_replays_with_changing_batches(bz):
+    """One batch object, graph mode: batches with different page counts and
+    kinds (forcing re-capture), each replayed several times with eager work
+    and synchronisation in between; every replay is checked."""
+    with bz.Batch(40) as B:
+        for rep, seed in enumerate([21, 22, 21, 23, 23]):
+            jobs = mixed_jobs(seed, 8 + 4 * (seed % 3), max_side=400)
+            expect = [single(bz, *j) for j in jobs]
+            for _ in range(2):
+                outs = run_batch(bz, B, jobs, use_graph=True)
+                for e, o in zip(expect, outs):
+                    assert np.array_equal(e, o), (rep, seed)
+                # eager work between replays
+                x = torch.randn(1000, device="cuda").sum()
+                torch.cuda.synchronize()
+                assert torch.isfinite(x)
+
+
+def test_config2_rgb_pages_batched(bz):
+    """A4 RGB pages (3508 x 2480), Sauvola win 31, k 0.34, in one launch."""
+    import pagegen
+    pages = pagegen.config2(n_pages=2)
+    jobs = [(p.img, p.win, f32(p.k), 128.0, 0) for p in pages] * 2
+    with bz.Batch(8) as B:
+        outs = run_batch(bz, B, jobs, use_graph=True)
+    for (img, win, k, R, rule), out in zip(jobs, outs):
+        assert np.array_equal(out, single(bz, img, win, k, R, rule))
+
+
+def test_batch_rejects_bad_pages(bz):
+    img = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    out = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    with bz.Batch(2, lds_cap=48 * 1024) as B:
+        with pytest.raises(bz.BinarizeError) as ei:
+            B.run([(img, out, 255, 0.5, 128.0, 0)])  # needs more LDS than the cap
+        assert ei.value.code == -9
+        with pytest.raises(bz.BinarizeError) as ei:
+            B.run([(img, out, 0, 0.5, 128.0, 0)])
+        assert ei.value.code == -4
+        with pytest.raises(bz.BinarizeError) as ei:
+            B.run([(img, out, 15, 0.5, 128.0, 0)] * 3)  # more pages than max_pages
+        assert ei.value.code == -2
+        B.run([(img, out, 15, 0.5, 128.0, 0)])  # still usable after errors
+        torch.cuda.synchronize()
+        assert torch.all(out == 255)
