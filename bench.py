@@ -141,7 +141,7 @@ def batch_jobs(name: str, dev):
     return jobs
 
 
-def run_batch_workload(name: str, reps: int) -> dict:
+def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) -> dict:
     """Per-image launches vs one persistent launch (direct and graph replay)
     on the same device-resident pages; outputs checked identical."""
     import torch
@@ -171,12 +171,16 @@ def run_batch_workload(name: str, reps: int) -> dict:
     ref = [j[1].clone() for j in jobs]
     res = {"workload": name, "pages": len(jobs), "pixels": px,
            "per_image": {"ms": ms_single, "gpix_s": px / ms_single / 1e6}}
-    with bz.Batch(len(jobs)) as B:
+    if tile_h:
+        jobs = [j[:6] + ((0, tile_h),) for j in jobs]
+    with bz.Batch(len(jobs), lds_cap=lds_cap) as B:
         for mode, graph in (("batch_direct", False), ("batch_graph", True)):
             ms = timed(lambda: B.run(jobs, use_graph=graph))
             same = all(torch.equal(r, j[1]) for r, j in zip(ref, jobs))
             res[mode] = {"ms": ms, "gpix_s": px / ms / 1e6, "identical_to_per_image": same}
         res["batch_grid"] = B.info()["grid"]
+        res["lds_cap"] = B.info()["lds_cap"]
+        res["batch_tile_h"] = tile_h or 128
     return res
 
 
@@ -189,6 +193,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--lds-cap", type=int, default=0, help="batch: LDS bytes per workgroup (0: default)")
+    ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
                     choices=["page4096", "batch-rgb", "batch-mixed"],
                     help="page4096: the metric line; batch-*: per-image vs persistent batch")
@@ -211,7 +217,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     bz.lib()
     if args.workload != "page4096":
-        print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20))), flush=True)
+        print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20), args.lds_cap,
+                                            args.batch_tile_h)), flush=True)
         return 0
 
     S = args.size

@@ -42,9 +42,10 @@ struct BatchPage {
 
 // Persistent workgroups of one tile variant pull items of that variant until
 // its counter passes n_items; every workgroup reaches that exit because the
-// counter only grows.
-template <int KIND>
-__global__ void __launch_bounds__(kThreads, 2)
+// counter only grows.  MINW is the occupancy the register budget is sized for
+// (waves per SIMD): 2 for LDS caps above a quarter of the CU's LDS, 4 below.
+template <int KIND, int MINW>
+__global__ void __launch_bounds__(kThreads, MINW)
     bz_batch_kernel(const BatchHeader *__restrict__ hdr, const BatchPage *__restrict__ all_pages,
                     uint32_t *__restrict__ counters) {
     constexpr int TW = (KIND & 4) ? 256 : 128;
@@ -76,10 +77,15 @@ __global__ void __launch_bounds__(kThreads, 2)
 }
 
 using BatchKernel = void (*)(const BatchHeader *, const BatchPage *, uint32_t *);
-const BatchKernel kBatchKernels[kKinds] = {
-    bz_batch_kernel<0>, bz_batch_kernel<1>, bz_batch_kernel<2>, bz_batch_kernel<3>,
-    bz_batch_kernel<4>, bz_batch_kernel<5>, bz_batch_kernel<6>, bz_batch_kernel<7>,
+const BatchKernel kBatchKernels[2][kKinds] = {
+    {bz_batch_kernel<0, 2>, bz_batch_kernel<1, 2>, bz_batch_kernel<2, 2>, bz_batch_kernel<3, 2>,
+     bz_batch_kernel<4, 2>, bz_batch_kernel<5, 2>, bz_batch_kernel<6, 2>, bz_batch_kernel<7, 2>},
+    {bz_batch_kernel<0, 4>, bz_batch_kernel<1, 4>, bz_batch_kernel<2, 4>, bz_batch_kernel<3, 4>,
+     bz_batch_kernel<4, 4>, bz_batch_kernel<5, 4>, bz_batch_kernel<6, 4>, bz_batch_kernel<7, 4>},
 };
+
+// LDS the batch kernels declare statically (the item slot), rounded up.
+constexpr int kStaticLds = 64;
 
 __global__ void bz_counter_reset(uint32_t *counters) {
     if (threadIdx.x < kKinds) counters[threadIdx.x] = 0u;
@@ -106,6 +112,7 @@ struct binarize_batch {
     hipGraphExec_t exec;
     int graph_mask;
     int kind_mask;          // kinds present in the last planned batch
+    int variant;            // 0: register budget for 2 workgroups per CU, 1: for 4
     hipEvent_t done;     // completion of the last run (guards the pinned table)
     bool pending;
     int last_items;
@@ -220,8 +227,8 @@ int record(binarize_batch *b, int mask, hipStream_t st) {
     const BatchPage *pg = (const BatchPage *)(hdr + 1);
     for (int q = 0; q < kKinds; ++q) {
         if (!(mask & (1 << q))) continue;
-        hipLaunchKernelGGL(kBatchKernels[q], dim3((unsigned)b->grid), dim3(kThreads), (unsigned)b->lds_cap, st, hdr,
-                           pg, b->counter);
+        hipLaunchKernelGGL(kBatchKernels[b->variant][q], dim3((unsigned)b->grid), dim3(kThreads),
+                           (unsigned)b->lds_cap, st, hdr, pg, b->counter);
     }
     e = hipGetLastError();
     return e == hipSuccess ? BZ_OK : fail(e);
@@ -235,18 +242,20 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out
     if (!out) return BZ_ERR_NULL;
     *out = nullptr;
     if (max_pages < 1 || max_pages > (1 << 20)) return BZ_ERR_SHAPE;
-    if (lds_cap_bytes <= 0) lds_cap_bytes = 80 * 1024;
-    // room for the item counter word kept in static LDS
-    if (lds_cap_bytes < tile_lds_bytes(128, 1) || lds_cap_bytes > kMaxLds - 64) return BZ_ERR_TILE;
+    // default: two workgroups per CU with their static LDS
+    if (lds_cap_bytes <= 0) lds_cap_bytes = kMaxLds / 2 - kStaticLds;
+    if (lds_cap_bytes < tile_lds_bytes(128, 1) || lds_cap_bytes > kMaxLds - kStaticLds) return BZ_ERR_TILE;
     binarize_batch *b = new (std::nothrow) binarize_batch();
     if (!b) return BZ_ERR_HIP;
     b->max_pages = max_pages;
     b->lds_cap = lds_cap_bytes;
+    b->variant = (lds_cap_bytes + kStaticLds) * 4 <= kMaxLds ? 1 : 0;
     b->table_bytes = sizeof(BatchHeader) + (size_t)max_pages * sizeof(BatchPage);
     hipError_t e = hipSuccess;
-    for (int q = 0; q < kKinds; ++q)
-        (void)hipFuncSetAttribute((const void *)kBatchKernels[q], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kMaxLds - 64);
+    for (int v = 0; v < 2; ++v)
+        for (int q = 0; q < kKinds; ++q)
+            (void)hipFuncSetAttribute((const void *)kBatchKernels[v][q], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      kMaxLds - kStaticLds);
     (void)hipGetLastError();
     int per_cu = 1 << 30, dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -256,8 +265,8 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out
     }
     for (int q = 0; q < kKinds; ++q) {  // the grid that fills the GPU for every kind
         int pc = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kBatchKernels[q], kThreads, lds_cap_bytes)) !=
-            hipSuccess) {
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kBatchKernels[b->variant][q], kThreads,
+                                                              lds_cap_bytes)) != hipSuccess) {
             delete b;
             return fail(e);
         }
