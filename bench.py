@@ -171,6 +171,12 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
     ref = [j[1].clone() for j in jobs]
     res = {"workload": name, "pages": len(jobs), "pixels": px,
            "per_image": {"ms": ms_single, "gpix_s": px / ms_single / 1e6}}
+    tuned = None
+    if lds_cap < 0:  # autotune cap and tile height for these shapes
+        from paper_1210_3165_amd.autotune import Tuner
+        specs = [(j[1].shape[0], j[1].shape[1], 1 if j[0].dim() == 2 else 3, j[2]) for j in jobs]
+        tuned = Tuner().batch_config(specs)
+        lds_cap, tile_h = tuned["lds_cap"], tuned["tile_h"]
     if tile_h:
         jobs = [j[:6] + ((0, tile_h),) for j in jobs]
     with bz.Batch(len(jobs), lds_cap=lds_cap) as B:
@@ -181,6 +187,7 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
         res["batch_grid"] = B.info()["grid"]
         res["lds_cap"] = B.info()["lds_cap"]
         res["batch_tile_h"] = tile_h or 128
+        res["autotuned"] = tuned is not None
     return res
 
 
@@ -193,7 +200,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--lds-cap", type=int, default=0, help="batch: LDS bytes per workgroup (0: default)")
+    ap.add_argument("--lds-cap", type=int, default=0,
+                    help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
                     choices=["page4096", "batch-rgb", "batch-mixed"],

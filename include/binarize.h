@@ -153,6 +153,10 @@ int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap,
                         int *last_items);
 void binarize_batch_destroy(binarize_batch *b);
 
+/* LDS bytes one workgroup of the given tile width needs for a window, or
+ * BZ_ERR_TILE if that tile cannot hold the window. */
+int binarize_tile_lds(int tile_w, int win);
+
 /* Default tile shape binarize/binarize_async pick for a problem. */
 int binarize_default_tile(int H, int W_img, int channels, int win,
                           int *tile_w, int *tile_h);

@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
-    "default_tile", "library_path", "lib", "Batch",
+    "default_tile", "tile_lds", "library_path", "lib", "Batch",
 ]
 
 SAUVOLA = 0
@@ -57,8 +57,10 @@ def lib() -> ctypes.CDLL:
     L.binarize_tuned.argtypes = [vp, i, i, i, i, f, f, i, vp, i, i, vp]
     L.binarize_stats.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, vp, vp, vp, vp, vp]
     L.binarize_default_tile.argtypes = [i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.binarize_tile_lds.argtypes = [i, i]
     for name in ("binarize", "binarize_async", "binarize_tuned", "binarize_stats",
-                 "binarize_default_tile", "binarize_version", "binarize_last_hip_error"):
+                 "binarize_default_tile", "binarize_version", "binarize_last_hip_error",
+                 "binarize_tile_lds"):
         getattr(L, name).restype = ctypes.c_int
     L.binarize_strerror.argtypes = [i]
     L.binarize_strerror.restype = ctypes.c_char_p
@@ -153,6 +155,13 @@ def binarize_stats(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule
     if rc:
         raise BinarizeError(rc, "binarize_stats")
     return res
+
+
+def tile_lds(tile_w: int, win: int) -> int | None:
+    """LDS bytes a workgroup of this tile width needs for the window, or None
+    if the tile cannot hold it."""
+    rc = lib().binarize_tile_lds(int(tile_w), int(win))
+    return None if rc < 0 else rc
 
 
 def default_tile(H: int, W: int, channels: int, win: int) -> tuple[int, int]:

@@ -217,6 +217,12 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels, int win, 
     return run(img, H, W_img, channels, win, k, R, rule, out, 0, 0, gray, s1, s2, n, t, true, stream);
 }
 
+int binarize_tile_lds(int tile_w, int win) {
+    if (win < 1 || win > 255) return BZ_ERR_WINDOW;
+    if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
+    return tile_lds_bytes(tile_w, win);
+}
+
 int binarize_default_tile(int H, int W_img, int channels, int win, int *tile_w, int *tile_h) {
     if (!tile_w || !tile_h) return BZ_ERR_NULL;
     if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
