@@ -191,6 +191,49 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
     return res
 
 
+def run_serve_workload(rates, duration: float, slots: int, max_pages: int) -> dict:
+    """Poisson request streams served twice on the same device-resident
+    inputs: continuous batching (persistent batched launches on `slots`
+    streams) and the plain form (one launch per request)."""
+    import torch
+
+    import pagegen
+    from paper_1210_3165_amd.serve import (GpuBatchExecutor, GpuSingleExecutor, Request, Server,
+                                           WallClock)
+    dev = torch.device("cuda:0")
+    canv = pagegen.device_canvases(dev)
+    free, _ = torch.cuda.mem_get_info(dev)
+    budget = int(min(free * 0.5, 32 << 30))
+
+    def requests(rate, seed):
+        rng = np.random.default_rng(seed)
+        out = []
+        for i, (t, H, W, C, win, k) in enumerate(pagegen.config4_stream(rate, duration, seed)):
+            r = Request(i, t, H, W, C, win, k)
+            r.img = pagegen.canvas_view(canv, H, W, C, rng)
+            out.append(r)
+        return out
+
+    def serve(mode, reqs):
+        ex = GpuBatchExecutor(slots, max_pages) if mode == "batched" else GpuSingleExecutor(slots)
+        clock = WallClock()
+        ex.start(clock)
+        st = Server(ex, budget, max_batch_pages=max_pages if mode == "batched" else 1).run(reqs, clock)
+        torch.cuda.synchronize()
+        ex.close()
+        return st.summary()
+
+    serve("batched", requests(1000.0, 1)[:100])  # warm-up (kernels loaded, pools filled)
+    serve("single", requests(1000.0, 1)[:100])
+    res = {"workload": "serve", "duration_s": duration, "slots": slots, "max_batch_pages": max_pages,
+           "hbm_budget_GB": budget / 1e9, "runs": []}
+    for rate in rates:
+        for mode in ("batched", "single"):
+            s = serve(mode, requests(rate, 5000 + int(rate)))
+            res["runs"].append({"rate": rate, "mode": mode, **s})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,8 +247,13 @@ def main() -> int:
                     help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
-                    choices=["page4096", "batch-rgb", "batch-mixed"],
-                    help="page4096: the metric line; batch-*: per-image vs persistent batch")
+                    choices=["page4096", "batch-rgb", "batch-mixed", "serve"],
+                    help="page4096: the metric line; batch-*: per-image vs persistent batch; "
+                         "serve: continuous batching vs one launch per request")
+    ap.add_argument("--rates", default="200,1000,5000", help="serve: Poisson rates, req/s")
+    ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds per rate and mode")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent batches (streams)")
+    ap.add_argument("--max-batch", type=int, default=32, help="serve: pages per micro-batch")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -224,6 +272,10 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     bz.lib()
+    if args.workload == "serve":
+        rates = [float(x) for x in args.rates.split(",")]
+        print(json.dumps(run_serve_workload(rates, args.duration, args.slots, args.max_batch)), flush=True)
+        return 0
     if args.workload != "page4096":
         print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20), args.lds_cap,
                                             args.batch_tile_h)), flush=True)

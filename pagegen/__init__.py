@@ -167,3 +167,33 @@ def config4_request(rng: np.random.Generator):
     channels = 3 if rng.random() < 0.5 else 1
     win = int(rng.integers(7, 76)) * 2 + 1  # odd, 15..151
     return H, W, channels, win, 0.5
+
+
+def config4_stream(rate: float, duration: float, seed: int, max_requests: int = 10_000):
+    """Poisson arrivals at `rate` req/s for `duration` s (or max_requests):
+    list of (arrival_s, H, W, channels, win, k) with the config4_request mix."""
+    rng = rng_for(seed)
+    t, out = 0.0, []
+    while len(out) < max_requests:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        H, W, C, win, k = config4_request(rng)
+        out.append((t, H, W, C, win, k))
+    return out
+
+
+def device_canvases(device):
+    """One gray and one RGB 4096 x 4096 page as flat device tensors; served
+    requests take contiguous H*W*C-byte views of them as their inputs."""
+    import torch
+    return {C: torch.from_numpy(page(4096, 4096, strokes_for(4096, 4096), seed=4000 + C,
+                                     channels=C).reshape(-1)).to(device) for C in (1, 3)}
+
+
+def canvas_view(canvases, H: int, W: int, C: int, rng: np.random.Generator):
+    n = H * W * C
+    base = canvases[C]
+    off = int(rng.integers(0, base.numel() - n + 1))
+    v = base[off:off + n]
+    return v.view(H, W) if C == 1 else v.view(H, W, 3)

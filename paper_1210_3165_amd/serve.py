@@ -1,0 +1,339 @@
+"""Serving loop with continuous batching for the binarizer.
+
+Requests (pages already resident in device memory) arrive over time.  The
+server:
+
+* admits them in arrival order while the HBM footprint of everything
+  admitted and not yet finished stays within a budget (footprint of a page =
+  input + output bytes = (C + 1) H W); a request larger than the whole budget
+  is refused;
+* whenever one of K execution slots is free, turns the admitted, not yet
+  dispatched requests into a micro-batch (bounded in pages and pixels) and
+  dispatches it, so requests that arrive while other batches run join the
+  next batch as soon as a slot frees up, and the batches of different slots
+  overlap on the device;
+* retires a batch when its completion event fires, releasing its footprint
+  and its output buffers, and records each request's latency (arrival to
+  completion on the GPU).
+
+Executors: ``GpuBatchExecutor`` (one persistent-launch batch object and one
+stream per slot), ``GpuSingleExecutor`` (the plain one-launch-per-request
+form, for comparison) and ``FakeExecutor`` (simulated time, used to test the
+scheduler on the CPU).
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds from the start of the run
+    H: int
+    W: int
+    C: int
+    win: int
+    k: float = 0.5
+    R: float = 128.0
+    rule: int = 0
+    img: object = None        # device tensor (GPU executors)
+    out: object = None        # filled by the executor
+    admitted: float = math.nan
+    dispatched: float = math.nan
+    done: float = math.nan
+    refused: bool = False
+    slot: int = -1
+
+    @property
+    def footprint(self) -> int:
+        return (self.C + 1) * self.H * self.W
+
+    @property
+    def pixels(self) -> int:
+        return self.H * self.W
+
+
+# ---------------------------------------------------------------------------
+# clocks
+# ---------------------------------------------------------------------------
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t: float) -> None:
+        while True:
+            d = t - self.now()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4) if d > 5e-4 else 0)
+
+
+class SimClock:
+    """Simulated time that jumps straight to the next event."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def wait_until(self, t: float) -> None:
+        self.t = max(self.t, t)
+
+
+# ---------------------------------------------------------------------------
+# scheduler
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ServeStats:
+    completed: list = field(default_factory=list)
+    refused: list = field(default_factory=list)
+    batches: int = 0
+    max_admitted_bytes: int = 0
+    max_queue: int = 0
+    batch_sizes: list = field(default_factory=list)
+
+    def summary(self) -> dict:
+        lat = np.array([r.done - r.arrival for r in self.completed]) if self.completed else np.zeros(1)
+        px = sum(r.pixels for r in self.completed)
+        span = (max(r.done for r in self.completed) - min(r.arrival for r in self.completed)) \
+            if self.completed else 0.0
+        return {
+            "requests": len(self.completed),
+            "refused": len(self.refused),
+            "batches": self.batches,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "max_ms": float(lat.max() * 1e3),
+            "gpix_s": px / span / 1e9 if span > 0 else 0.0,
+            "req_s": len(self.completed) / span if span > 0 else 0.0,
+            "max_admitted_MB": self.max_admitted_bytes / 1e6,
+            "max_queue": self.max_queue,
+        }
+
+
+class Server:
+    def __init__(self, executor, hbm_budget: int, max_batch_pages: int = 64,
+                 max_batch_pixels: int = 64 * 2**20):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_pages = int(max_batch_pages)
+        self.max_pixels = int(max_batch_pixels)
+
+    def run(self, requests, clock) -> ServeStats:
+        st = ServeStats()
+        incoming = deque(sorted(requests, key=lambda r: r.arrival))
+        arrived = deque()      # arrived, waiting for admission (footprint)
+        admitted = deque()     # admitted, waiting for a slot
+        free = list(range(self.ex.slots))
+        inflight = {}          # slot -> list of requests
+        used = 0               # admitted footprint bytes
+        while incoming or arrived or admitted or inflight:
+            now = clock.now()
+            while incoming and incoming[0].arrival <= now:
+                arrived.append(incoming.popleft())
+            # admission by footprint, in arrival order
+            while arrived:
+                r = arrived[0]
+                if r.footprint > self.budget:
+                    arrived.popleft()
+                    r.refused = True
+                    st.refused.append(r)
+                    continue
+                if used + r.footprint > self.budget:
+                    break
+                arrived.popleft()
+                used += r.footprint
+                r.admitted = now
+                admitted.append(r)
+            st.max_admitted_bytes = max(st.max_admitted_bytes, used)
+            st.max_queue = max(st.max_queue, len(arrived) + len(admitted))
+            # continuous batching: every free slot takes the next micro-batch
+            while free and admitted:
+                batch, px = [], 0
+                while admitted and len(batch) < self.max_pages and \
+                        (not batch or px + admitted[0].pixels <= self.max_pixels):
+                    r = admitted.popleft()
+                    px += r.pixels
+                    batch.append(r)
+                slot = free.pop()
+                for r in batch:
+                    r.dispatched = now
+                    r.slot = slot
+                self.ex.submit(slot, batch, now)
+                inflight[slot] = batch
+                st.batches += 1
+                st.batch_sizes.append(len(batch))
+            # completions, in whatever order they finish
+            for slot, t_done in self.ex.poll(now):
+                for r in inflight.pop(slot):
+                    r.done = t_done
+                    used -= r.footprint
+                    st.completed.append(r)
+                self.ex.release(slot)
+                free.append(slot)
+            if not (incoming or arrived or admitted or inflight):
+                break
+            nxt = self.ex.next_event(now)
+            if incoming:
+                nxt = min(nxt, incoming[0].arrival)
+            if nxt > now:
+                clock.wait_until(nxt)
+        return st
+
+
+# ---------------------------------------------------------------------------
+# executors
+# ---------------------------------------------------------------------------
+
+class FakeExecutor:
+    """Simulated device: a batch on a slot takes latency + pixels / rate
+    seconds, independent of the other slots; `jitter(n)` scales the n-th
+    batch's duration so a test can make later batches finish first."""
+
+    def __init__(self, slots: int, rate_px_s: float = 2e11, latency_s: float = 20e-6, jitter=None):
+        self.slots = slots
+        self.rate = rate_px_s
+        self.latency = latency_s
+        self.jitter = jitter
+        self.finish = {}
+        self.submitted = []
+
+    def submit(self, slot, batch, now):
+        dur = self.latency + sum(r.pixels for r in batch) / self.rate
+        if self.jitter is not None:
+            dur *= self.jitter(len(self.submitted))
+        self.finish[slot] = now + dur
+        self.submitted.append((slot, [r.rid for r in batch], now))
+
+    def poll(self, now):
+        done = sorted((t, s) for s, t in self.finish.items() if t <= now)
+        for t, s in done:
+            del self.finish[s]
+        return [(s, t) for t, s in done]
+
+    def release(self, slot):
+        pass
+
+    def next_event(self, now):
+        return min(self.finish.values()) if self.finish else now + 1e-3
+
+
+class _BufferPool:
+    """Device output buffers in power-of-two size classes, reused after the
+    batch that wrote them retires."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.free = {}
+        self.bytes = 0
+
+    def get(self, n: int):
+        cls = 1 << max(12, (n - 1).bit_length())
+        lst = self.free.setdefault(cls, [])
+        if lst:
+            return lst.pop()
+        self.bytes += cls
+        return self.torch.empty(cls, dtype=self.torch.uint8, device=self.device)
+
+    def put(self, buf):
+        self.free.setdefault(buf.numel(), []).append(buf)
+
+
+class _GpuBase:
+    def __init__(self, slots: int, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.slots = slots
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.pool = _BufferPool(self.device)
+        self.ev = {}
+        self.bufs = {}
+        # time reference: GPU timestamps are converted to the server clock
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+
+    def start(self, clock):
+        """Align GPU event time with the server clock (call right after the
+        clock is created)."""
+        self.t0_event.record(self.torch.cuda.current_stream(self.device))
+        self.t0_event.synchronize()
+        self.t0 = clock.now()
+
+    def _outs(self, slot, batch):
+        bufs = []
+        for r in batch:
+            b = self.pool.get(r.pixels)
+            bufs.append(b)
+            r.out = b[:r.pixels].view(r.H, r.W)
+        self.bufs[slot] = bufs
+
+    def poll(self, now):
+        res = []
+        for slot, e in list(self.ev.items()):
+            if e.query():
+                res.append((slot, self.t0 + self.t0_event.elapsed_time(e) / 1e3))
+                del self.ev[slot]
+        return res
+
+    def release(self, slot):
+        for b in self.bufs.pop(slot, []):
+            self.pool.put(b)
+
+    def next_event(self, now):
+        return now + 5e-5 if self.ev else now + 1e-3
+
+    def _finish(self, slot):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record(self.streams[slot])
+        self.ev[slot] = e
+
+
+class GpuBatchExecutor(_GpuBase):
+    """One persistent launch per micro-batch; each slot owns a stream and a
+    batch object, so batches of different slots run concurrently."""
+
+    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None):
+        super().__init__(slots, device)
+        from . import Batch
+        self.batches = [Batch(max_pages, lds_cap=lds_cap, device=self.device) for _ in range(slots)]
+
+    def submit(self, slot, batch, now):
+        self._outs(slot, batch)
+        jobs = [(r.img, r.out, r.win, r.k, r.R, r.rule) for r in batch]
+        with self.torch.cuda.stream(self.streams[slot]):
+            self.batches[slot].run(jobs, use_graph=False, stream=self.streams[slot])
+        self._finish(slot)
+
+    def close(self):
+        for b in self.batches:
+            b.close()
+
+
+class GpuSingleExecutor(_GpuBase):
+    """The plain form: one launch per request, requests dispatched one at a
+    time (max_batch_pages should be 1), round-robin over the slots' streams."""
+
+    def submit(self, slot, batch, now):
+        from . import binarize
+        self._outs(slot, batch)
+        for r in batch:
+            binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
+        self._finish(slot)
+
+    def close(self):
+        pass

@@ -1,0 +1,94 @@
+"""Serving loop: the scheduler on a simulated device (CPU) and a real mix on
+the GPU whose every result equals the page binarized alone."""
+import numpy as np
+import pytest
+
+from paper_1210_3165_amd.serve import FakeExecutor, Request, Server, SimClock
+
+
+def reqs(specs):
+    return [Request(i, t, H, W, C, win) for i, (t, H, W, C, win) in enumerate(specs)]
+
+
+def test_every_request_completes_once_and_latency_is_consistent():
+    rng = np.random.default_rng(0)
+    specs = [(float(t), int(rng.integers(100, 2000)), int(rng.integers(100, 2000)), int(rng.choice([1, 3])), 31)
+             for t in np.cumsum(rng.exponential(1e-3, 500))]
+    rs = reqs(specs)
+    st = Server(FakeExecutor(slots=4, rate_px_s=5e9), hbm_budget=1 << 30).run(rs, SimClock())
+    assert len(st.completed) == 500 and not st.refused
+    assert sorted(r.rid for r in st.completed) == list(range(500))
+    for r in st.completed:
+        assert r.arrival <= r.admitted <= r.dispatched <= r.done
+    s = st.summary()
+    assert 0 < s["p50_ms"] <= s["p99_ms"] <= s["max_ms"]
+
+
+def test_admission_respects_the_footprint_budget_and_refuses_oversize():
+    budget = 40_000_000
+    big = Request(0, 0.0, 5000, 5000, 3, 15)          # 100 MB > budget: refused
+    rs = [big] + [Request(i, 0.0, 2000, 2000, 1, 15) for i in range(1, 30)]  # 8 MB each
+    st = Server(FakeExecutor(slots=8, rate_px_s=1e8), hbm_budget=budget).run(rs, SimClock())
+    assert [r.rid for r in st.refused] == [0]
+    assert len(st.completed) == 29
+    assert st.max_admitted_bytes <= budget
+    # at most 5 requests (40 MB) fit at once: some had to wait for admission
+    assert any(r.admitted > r.arrival for r in st.completed)
+
+
+def test_slot_exhaustion_forms_bigger_batches():
+    """One slot and a burst: the first batch holds the first arrival, every
+    request that arrives meanwhile joins the next batch (continuous batching)."""
+    rs = [Request(i, i * 1e-5, 1000, 1000, 1, 15) for i in range(40)]
+    ex = FakeExecutor(slots=1, rate_px_s=1e9)  # 1 ms per page
+    st = Server(ex, hbm_budget=1 << 30, max_batch_pages=64).run(rs, SimClock())
+    assert len(st.completed) == 40
+    assert st.batches < 10 and max(st.batch_sizes) > 10
+    slots_busy = [s for s, _, _ in ex.submitted]
+    assert set(slots_busy) == {0}
+
+
+def test_out_of_order_completion():
+    """Later batches finishing first must not confuse the bookkeeping."""
+    order = {0: 50.0, 1: 1.0, 2: 0.2, 3: 1.0}
+    rs = [Request(i, i * 1e-4, 500, 500, 1, 15) for i in range(60)]
+    ex = FakeExecutor(slots=4, rate_px_s=1e9, jitter=lambda n: order.get(n % 4, 1.0))
+    st = Server(ex, hbm_budget=1 << 30, max_batch_pages=4).run(rs, SimClock())
+    assert sorted(r.rid for r in st.completed) == list(range(60))
+    done_order = [r.rid for r in st.completed]
+    assert done_order != sorted(done_order)  # completions really were reordered
+    for r in st.completed:
+        assert r.done >= r.dispatched
+
+
+@pytest.mark.gpu
+def test_gpu_served_mix_equals_pages_alone():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import pagegen
+    import paper_1210_3165_amd as bz
+    from paper_1210_3165_amd.serve import GpuBatchExecutor, WallClock
+    dev = torch.device("cuda:0")
+    canv = pagegen.device_canvases(dev)
+    rng = np.random.default_rng(3)
+    stream = pagegen.config4_stream(2000.0, 0.05, seed=4)
+    rs = []
+    for i, (t, H, W, C, win, k) in enumerate(stream):
+        H, W = min(H, 1500), min(W, 1500)  # keep the test light
+        r = Request(i, t, H, W, C, win, k, rule=i % 2)
+        r.img = pagegen.canvas_view(canv, H, W, C, rng)
+        rs.append(r)
+    assert len(rs) > 40
+    ex = GpuBatchExecutor(slots=3, max_pages=16)
+    clock = WallClock()
+    ex.start(clock)
+    st = Server(ex, hbm_budget=256 << 20, max_batch_pages=16).run(rs, clock)
+    torch.cuda.synchronize()
+    assert len(st.completed) == len(rs) and not st.refused
+    assert max(st.batch_sizes) > 1  # requests really were served in mixes
+    outs = {r.rid: r.out.clone() for r in st.completed}
+    for r in rs:
+        alone = bz.binarize(r.img, r.win, r.k, r.R, r.rule)
+        assert torch.equal(alone, outs[r.rid]), r.rid
+    ex.close()
