@@ -132,7 +132,11 @@ class Server:
         self.max_pages = int(max_batch_pages)
         self.max_pixels = int(max_batch_pixels)
 
-    def run(self, requests, clock) -> ServeStats:
+    def run(self, requests, clock, on_done=None) -> ServeStats:
+        """Serve `requests` (sorted by arrival or not) on `clock`.  on_done(r)
+        is called for every finished request while r.out still holds its
+        result; the output buffer is recycled as soon as on_done returns, so
+        the result must be consumed (copied, written out) inside it."""
         st = ServeStats()
         incoming = deque(sorted(requests, key=lambda r: r.arrival))
         arrived = deque()      # arrived, waiting for admission (footprint)
@@ -182,6 +186,9 @@ class Server:
                     r.done = t_done
                     used -= r.footprint
                     st.completed.append(r)
+                    if on_done is not None:
+                        on_done(r)
+                    r.out = None  # the buffer goes back to the pool
                 self.ex.release(slot)
                 free.append(slot)
             if not (incoming or arrived or admitted or inflight):
@@ -305,7 +312,9 @@ class _GpuBase:
 
 class GpuBatchExecutor(_GpuBase):
     """One persistent launch per micro-batch; each slot owns a stream and a
-    batch object, so batches of different slots run concurrently."""
+    batch object, so batches of different slots run concurrently.  A
+    micro-batch of a single page goes through the plain single-page launch,
+    which skips the batch's table copy and counter reset."""
 
     def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None):
         super().__init__(slots, device)
@@ -314,8 +323,12 @@ class GpuBatchExecutor(_GpuBase):
 
     def submit(self, slot, batch, now):
         self._outs(slot, batch)
-        jobs = [(r.img, r.out, r.win, r.k, r.R, r.rule) for r in batch]
-        with self.torch.cuda.stream(self.streams[slot]):
+        if len(batch) == 1:
+            from . import binarize
+            r = batch[0]
+            binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
+        else:
+            jobs = [(r.img, r.out, r.win, r.k, r.R, r.rule) for r in batch]
             self.batches[slot].run(jobs, use_graph=False, stream=self.streams[slot])
         self._finish(slot)
 

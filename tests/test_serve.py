@@ -76,18 +76,24 @@ def test_gpu_served_mix_equals_pages_alone():
     rs = []
     for i, (t, H, W, C, win, k) in enumerate(stream):
         H, W = min(H, 1500), min(W, 1500)  # keep the test light
+        t = (i // 6) * 2e-3  # bursts of 6 simultaneous arrivals force mixed batches
         r = Request(i, t, H, W, C, win, k, rule=i % 2)
         r.img = pagegen.canvas_view(canv, H, W, C, rng)
         rs.append(r)
     assert len(rs) > 40
-    ex = GpuBatchExecutor(slots=3, max_pages=16)
+    ex = GpuBatchExecutor(slots=2, max_pages=16)
     clock = WallClock()
     ex.start(clock)
-    st = Server(ex, hbm_budget=256 << 20, max_batch_pages=16).run(rs, clock)
+    outs = {}
+
+    def keep(r):  # consume the result before its buffer is recycled
+        outs[r.rid] = r.out.clone()
+        torch.cuda.current_stream().synchronize()
+
+    st = Server(ex, hbm_budget=256 << 20, max_batch_pages=16).run(rs, clock, on_done=keep)
     torch.cuda.synchronize()
     assert len(st.completed) == len(rs) and not st.refused
     assert max(st.batch_sizes) > 1  # requests really were served in mixes
-    outs = {r.rid: r.out.clone() for r in st.completed}
     for r in rs:
         alone = bz.binarize(r.img, r.win, r.k, r.R, r.rule)
         assert torch.equal(alone, outs[r.rid]), r.rid
