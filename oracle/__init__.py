@@ -7,7 +7,7 @@ Python binding) never touches it, and the two share no code.
 The arithmetic lives in ``oracle.c`` (plain C, double precision, a direct
 window loop per pixel); this module only builds it with gcc and marshals NumPy
 arrays through ctypes.  See ``oracle.c`` for the definitions it follows
-(Sec. 1 Eq. 1, 3, 4 and Sec. 2 of the paper).
+(Sec. 1 Eq. 1, 2, 3, 4 and Sec. 2 of the paper).
 """
 from __future__ import annotations
 
@@ -62,6 +62,9 @@ def _load():
                                            u8p, u32p, u32p, u32p, f64p, f64p, f64p, u8p]
     lib.oracle_binarize_points.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_otsu.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
+                                ctypes.POINTER(ctypes.c_int), u8p]
+    lib.oracle_otsu.restype = ctypes.c_int
     lib.oracle_version.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -159,3 +162,17 @@ def binarize_points(img: np.ndarray, win: int, k: float, R: float, rule: int,
 def num_threads() -> int:
     """OpenMP threads the oracle uses on this host."""
     return int(_load().oracle_num_threads())
+
+
+def otsu(img: np.ndarray):
+    """Otsu's global threshold (Sec. 1, Eq. 2 baseline): returns (T, k*, hist,
+    out) with out = 0 where f < T = k* + 1."""
+    img, H, W, C = _as_image(img)
+    hist = np.empty(256, np.uint32)
+    out = np.empty((H, W), np.uint8)
+    k = ctypes.c_int()
+    T = _load().oracle_otsu(_ptr(img, ctypes.c_uint8), H, W, C, _ptr(hist, ctypes.c_uint32),
+                            ctypes.byref(k), _ptr(out, ctypes.c_uint8))
+    if T < 0:
+        raise ValueError(f"oracle_otsu failed ({T})")
+    return T, k.value, hist, out

@@ -23,6 +23,10 @@
  *     Niblack: t = m + k s;
  *   - binary output (Sec. 1, Eq. 3): g = 0 if f < t, 255 otherwise.
  *
+ * And, for the paper's global baseline (Sec. 1, Eq. 2), Otsu's threshold:
+ * the 256-bin histogram of f, the split level k* of largest between-class
+ * variance and g = 0 if f < T = k* + 1 (oracle_otsu).
+ *
  * Window placement: rows [y - lo, y + hi], columns [x - lo, x + hi] with
  * lo = floor(win / 2), hi = win - 1 - lo, intersected with the image.
  *
@@ -223,4 +227,58 @@ int oracle_num_threads(void) {
         }
     }
     return nt;
+}
+
+/*
+ * Otsu's global threshold (the global baseline of Sec. 1, Eq. 2, whose
+ * threshold the paper takes from Otsu's method).  From the 256-bin histogram
+ * h of the gray levels (N pixels), for every level k the two classes are
+ * C0 = {f <= k} and C1 = {f > k} with
+ *   w0 = n0 / N, w1 = n1 / N, mu0 = S0 / n0, mu1 = S1 / n1
+ * (n = pixel count, S = sum of levels of the class), and the between-class
+ * variance is  sigma_b^2(k) = w0 w1 (mu0 - mu1)^2  (0 if a class is empty).
+ * k* is the first level reaching the maximum; Eq. 2 then binarizes with
+ * T = k* + 1 (g = 0 if f < T, i.e. f <= k*; 255 otherwise).
+ * hist (256 u32), kstar and out may be NULL.  Returns T.
+ */
+static double otsu_sigma(uint64_t n0, uint64_t s0, uint64_t n, uint64_t s) {
+    const uint64_t n1 = n - n0, s1 = s - s0;
+    if (n0 == 0 || n1 == 0) return 0.0;
+    const double w0 = (double)n0 / (double)n, w1 = (double)n1 / (double)n;
+    const double mu0 = (double)s0 / (double)n0, mu1 = (double)s1 / (double)n1;
+    const double d = mu0 - mu1;
+    return w0 * w1 * (d * d);
+}
+
+int oracle_otsu(const uint8_t *img, int H, int W, int channels, uint32_t *hist, int *kstar,
+                uint8_t *out) {
+    if (!img || H < 1 || W < 1 || (channels != 1 && channels != 3)) return OR_ERR_ARG;
+    size_t npx = (size_t)H * (size_t)W;
+    uint8_t *f = (uint8_t *)malloc(npx);
+    if (!f) return OR_ERR_NOMEM;
+    oracle_gray(img, H, W, channels, f);
+    uint64_t h[256] = {0};
+    for (size_t i = 0; i < npx; ++i) h[f[i]]++;
+    uint64_t n = npx, s = 0;
+    for (int v = 0; v < 256; ++v) s += (uint64_t)v * h[v];
+    int best = 0;
+    double best_sigma = -1.0;
+    uint64_t n0 = 0, s0 = 0;
+    for (int k = 0; k < 256; ++k) {
+        n0 += h[k];
+        s0 += (uint64_t)k * h[k];
+        const double sg = otsu_sigma(n0, s0, n, s);
+        if (sg > best_sigma) {
+            best_sigma = sg;
+            best = k;
+        }
+    }
+    const int T = best + 1;
+    if (hist)
+        for (int v = 0; v < 256; ++v) hist[v] = (uint32_t)h[v];
+    if (kstar) *kstar = best;
+    if (out)
+        for (size_t i = 0; i < npx; ++i) out[i] = f[i] < T ? 0 : 255; /* Eq. 2 */
+    free(f);
+    return T;
 }
