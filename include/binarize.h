@@ -153,6 +153,39 @@ int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap,
                         int *last_items);
 void binarize_batch_destroy(binarize_batch *b);
 
+/*
+ * Otsu global threshold -- the paper's global baseline (Sec. 1, Eq. 2),
+ * whose single threshold T comes from Otsu's method.  From the 256-bin
+ * histogram of the Eq. 1 gray levels f, every split level k defines the
+ * classes {f <= k} and {f > k}; k* is the first level with the largest
+ * between-class variance w0 w1 (mu0 - mu1)^2 (w = class share of the pixels,
+ * mu = class mean; 0 when a class is empty, so k* = 0 if nothing can be
+ * separated), evaluated in fp64.  T = k* + 1 and out = 0 where f < T, 255
+ * elsewhere.
+ *
+ * binarize_otsu -- img: device, H x W_img x channels (layout as above).
+ *   out: device, H x W_img, or NULL to compute only the histogram and T.
+ *   ws: device workspace of at least BZ_OTSU_WS_BYTES bytes, 16-byte aligned,
+ *   owned by the caller; it needs no initialisation (every call rewrites
+ *   what it reads).  After the call (in stream order) ws holds, as u32
+ *   words, the histogram at BZ_OTSU_WS_HIST (256 words), T at BZ_OTSU_WS_T
+ *   and k* at BZ_OTSU_WS_KSTAR; the rest is scratch.  Calls that share a
+ *   workspace must be ordered (same stream, or synchronised).  Three
+ *   launches (histogram, selection, decision; two if out is NULL); no
+ *   allocation.  Errors: BZ_ERR_NULL (img), BZ_ERR_WORKSPACE (ws NULL, too
+ *   small or misaligned), BZ_ERR_SHAPE, BZ_ERR_CHANNELS, BZ_ERR_ALIAS (out,
+ *   img and ws must not overlap), BZ_ERR_HIP.
+ * binarize_otsu_workspace_size -- BZ_OTSU_WS_BYTES.
+ */
+#define BZ_OTSU_WS_BYTES (4096 + 512 * 1024)
+#define BZ_OTSU_WS_HIST 0
+#define BZ_OTSU_WS_T 256
+#define BZ_OTSU_WS_KSTAR 257
+
+int binarize_otsu(const uint8_t *img, int H, int W_img, int channels, uint8_t *out,
+                  uint32_t *ws, size_t ws_bytes, void *stream);
+size_t binarize_otsu_workspace_size(void);
+
 /* LDS bytes one workgroup of the given tile width needs for a window, or
  * BZ_ERR_TILE if that tile cannot hold the window. */
 int binarize_tile_lds(int tile_w, int win);

@@ -4,8 +4,10 @@ Thin Python binding over ``libbinarize.so`` (C ABI in ``include/binarize.h``):
 argument marshalling only.  Every step of the computation -- Eq. 1 gray
 conversion, exact window sums, the Eq. 4 / Niblack threshold and the Eq. 3
 decision of Mollah, Basu and Nasipuri (arXiv:1210.3165) -- runs in the HIP
-kernels.  PyTorch supplies device memory and streams; there is no CPU
-fallback: without the built library every call raises.
+kernels, and so does the global baseline the paper compares against
+(Otsu's threshold with the Eq. 2 decision).  PyTorch supplies device memory
+and streams; there is no CPU fallback: without the built library every call
+raises.
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ import torch
 
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
-    "default_tile", "tile_lds", "library_path", "lib", "Batch",
+    "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu",
 ]
 
 SAUVOLA = 0
@@ -268,3 +270,80 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Otsu global threshold (the paper's global baseline)
+# ---------------------------------------------------------------------------
+
+OTSU_WS_WORDS = (4096 + 512 * 1024) // 4  # BZ_OTSU_WS_BYTES / 4
+OTSU_WS_HIST, OTSU_WS_T, OTSU_WS_KSTAR = 0, 256, 257
+
+
+def _otsu_lib() -> ctypes.CDLL:
+    L = lib()
+    if not getattr(L, "_otsu_ready", False):
+        vp, i = ctypes.c_void_p, ctypes.c_int
+        L.binarize_otsu.argtypes = [vp, i, i, i, vp, vp, ctypes.c_size_t, vp]
+        L.binarize_otsu.restype = i
+        L.binarize_otsu_workspace_size.argtypes = []
+        L.binarize_otsu_workspace_size.restype = ctypes.c_size_t
+        if L.binarize_otsu_workspace_size() != 4 * OTSU_WS_WORDS:
+            raise ImportError("libbinarize.so has a different Otsu workspace size; rebuild it")
+        L._otsu_ready = True
+    return L
+
+
+class Otsu:
+    """Otsu's global threshold (``binarize_otsu`` in the C ABI) with its own
+    device workspace.  ``run`` enqueues the histogram, the selection of T and
+    (unless ``threshold_only``) the Eq. 2 decision on the stream; afterwards
+    ``hist``, ``T`` and ``kstar`` read the workspace (``T``/``kstar`` sync).
+    Calls on one object must be ordered (one stream, or synchronised)."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        _otsu_lib()
+        self.ws = torch.empty(OTSU_WS_WORDS, dtype=torch.int32, device=self.device)
+
+    def run(self, img: torch.Tensor, out: torch.Tensor | None = None, threshold_only: bool = False,
+            stream: torch.cuda.Stream | None = None) -> torch.Tensor | None:
+        H, W, C = _check_image(img)
+        if img.device != self.device:
+            raise ValueError("img is on another device than the workspace")
+        if threshold_only:
+            out = None
+        elif out is None:
+            out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+        elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+        with torch.cuda.device(self.device):
+            s = ctypes.c_void_p(_stream_ptr(stream, self.device))
+            rc = _otsu_lib().binarize_otsu(_ptr(img), H, W, C, _ptr(out), _ptr(self.ws),
+                                           4 * OTSU_WS_WORDS, s)
+        if rc:
+            raise BinarizeError(rc, "binarize_otsu")
+        return out
+
+    @property
+    def hist(self) -> torch.Tensor:
+        """Histogram of the last run's gray levels (256 counts, device)."""
+        return self.ws[OTSU_WS_HIST:OTSU_WS_HIST + 256]
+
+    @property
+    def T(self) -> int:
+        return int(self.ws[OTSU_WS_T].item())
+
+    @property
+    def kstar(self) -> int:
+        return int(self.ws[OTSU_WS_KSTAR].item())
+
+
+def otsu(img: torch.Tensor, out: torch.Tensor | None = None,
+         stream: torch.cuda.Stream | None = None) -> tuple[torch.Tensor, int]:
+    """Binarize with Otsu's global threshold; returns (out, T).  Synchronises
+    to read T; use ``Otsu`` to keep everything on the stream."""
+    o = Otsu(img.device)
+    out = o.run(img, out, stream=stream)
+    return out, o.T

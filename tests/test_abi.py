@@ -116,3 +116,34 @@ def test_python_binding_refuses_cpu_tensors():
         bz.binarize(torch.zeros((8, 8), dtype=torch.uint8), 3, 0.5)
     with pytest.raises(TypeError):
         bz.binarize(torch.zeros((8, 8), dtype=torch.float32), 3, 0.5)
+
+
+FAKE_WS = 0x30000000
+WS = 4096 + 512 * 1024  # BZ_OTSU_WS_BYTES
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 16, 16, 1, FAKE_OUT, FAKE_WS, WS), -1),              # null img
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, None, WS), -10),             # null workspace
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, FAKE_WS, WS - 1), -10),      # workspace too small
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, FAKE_WS + 2, WS), -10),      # misaligned workspace
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, FAKE_WS + 4, WS), -10),      # not 16-byte aligned
+    ((FAKE_IN, 0, 16, 1, FAKE_OUT, FAKE_WS, WS), -2),            # H < 1
+    ((FAKE_IN, 65536, 32768, 1, FAKE_OUT, FAKE_WS, WS), -2),     # 2^31 pixels
+    ((FAKE_IN, 16, 16, 2, FAKE_OUT, FAKE_WS, WS), -3),           # two channels
+    ((FAKE_IN, 16, 16, 3, FAKE_IN + 700, FAKE_WS, WS), -7),      # out inside the RGB img
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, FAKE_IN + 208, WS), -7),     # workspace over img
+    ((FAKE_IN, 16, 16, 1, FAKE_OUT, FAKE_OUT - 112, WS), -7),    # workspace over out
+])
+def test_otsu_invalid_arguments(L, args, code):
+    vp = ctypes.c_void_p
+    L.binarize_otsu.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
+                                ctypes.c_size_t, vp]
+    a = [vp(x) if i in (0, 4, 5) else x for i, x in enumerate(args)]
+    assert L.binarize_otsu(*a, None) == code
+
+
+def test_otsu_workspace_contract(L):
+    vp = ctypes.c_void_p
+    L.binarize_otsu_workspace_size.restype = ctypes.c_size_t
+    assert L.binarize_otsu_workspace_size() == WS
