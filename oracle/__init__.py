@@ -7,7 +7,7 @@ Python binding) never touches it, and the two share no code.
 The arithmetic lives in ``oracle.c`` (plain C, double precision, a direct
 window loop per pixel); this module only builds it with gcc and marshals NumPy
 arrays through ctypes.  See ``oracle.c`` for the definitions it follows
-(Sec. 1 Eq. 1, 2, 3, 4 and Sec. 2 of the paper).
+(Sec. 1 Eq. 1, 2, 3, 4, Sec. 2 Eq. 5 and Sec. 3 Eq. 6 of the paper).
 """
 from __future__ import annotations
 
@@ -65,6 +65,10 @@ def _load():
     lib.oracle_otsu.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, u32p,
                                 ctypes.POINTER(ctypes.c_int), u8p]
     lib.oracle_otsu.restype = ctypes.c_int
+    lib.oracle_binarize_gs.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       u32p, u32p, u32p, f64p, u8p]
+    lib.oracle_binarize_gs.restype = ctypes.c_int
     lib.oracle_version.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -176,3 +180,45 @@ def otsu(img: np.ndarray):
     if T < 0:
         raise ValueError(f"oracle_otsu failed ({T})")
     return T, k.value, hist, out
+
+
+GS_PLUS, GS_X, GS_STAR = 0, 1, 2
+
+
+def binarize_gs(img: np.ndarray, win: int, k: float, Rp: float, structure: int) -> OracleResult:
+    """Sampled-window Sauvola (Sec. 2, Eq. 5) over the structure's members of
+    the odd win x win window: s1, s2, n, t and out (gray, m, s are None)."""
+    img, H, W, C = _as_image(img)
+    s1 = np.empty((H, W), np.uint32)
+    s2 = np.empty((H, W), np.uint32)
+    n = np.empty((H, W), np.uint32)
+    t = np.empty((H, W), np.float64)
+    out = np.empty((H, W), np.uint8)
+    rc = _load().oracle_binarize_gs(_ptr(img, ctypes.c_uint8), H, W, C, int(win), float(k), float(Rp),
+                                    int(structure), _ptr(s1, ctypes.c_uint32), _ptr(s2, ctypes.c_uint32),
+                                    _ptr(n, ctypes.c_uint32), _ptr(t, ctypes.c_double),
+                                    _ptr(out, ctypes.c_uint8))
+    if rc:
+        raise ValueError(f"oracle_binarize_gs failed ({rc})")
+    return OracleResult(None, s1, s2, n, None, None, t, out)
+
+
+def fmeasure_counts(out: np.ndarray, gt: np.ndarray) -> tuple[int, int, int]:
+    """(TP, FP, FN) of a binarized page against its ground truth (Sec. 3).
+    Foreground is text: output 0 (f < t, Eq. 3) and gt != 0."""
+    fg = np.asarray(out) == 0
+    truth = np.asarray(gt) != 0
+    tp = int(np.count_nonzero(fg & truth))
+    fp = int(np.count_nonzero(fg & ~truth))
+    fn = int(np.count_nonzero(~fg & truth))
+    return tp, fp, fn
+
+
+def fmeasure(tp: int, fp: int, fn: int) -> float:
+    """Eq. 6: FM = 2 R P / (R + P), R = TP / (TP + FN), P = TP / (TP + FP);
+    0 when there is no true positive."""
+    if tp == 0:
+        return 0.0
+    R = tp / (tp + fn)
+    P = tp / (tp + fp)
+    return 2 * R * P / (R + P)

@@ -27,6 +27,9 @@
  * the 256-bin histogram of f, the split level k* of largest between-class
  * variance and g = 0 if f < T = k* + 1 (oracle_otsu).
  *
+ * And the sampled-window variant of Sec. 2 (Eq. 5) over this library's own
+ * O(W) structures (oracle_binarize_gs).
+ *
  * Window placement: rows [y - lo, y + hi], columns [x - lo, x + hi] with
  * lo = floor(win / 2), hi = win - 1 - lo, intersected with the image.
  *
@@ -281,4 +284,89 @@ int oracle_otsu(const uint8_t *img, int H, int W, int channels, uint32_t *hist, 
         for (size_t i = 0; i < npx; ++i) out[i] = f[i] < T ? 0 : 255; /* Eq. 2 */
     free(f);
     return T;
+}
+
+/*
+ * Sampled-window variant (Sec. 2, Eq. 5).  The paper replaces the window S by
+ * a subset S' of O(W) pixels picked by a geometric structure (its Fig. 1,
+ * whose drawings are not available).  The structures here are this
+ * library's own, for odd win (lo = hi = win / 2), offsets (dy, dx) of the
+ * window with
+ *   structure 0 "plus":  dy == 0 or dx == 0          (centre row + column)
+ *   structure 1 "x":     dy == dx or dy == -dx       (both diagonals)
+ *   structure 2 "star":  the union of the two
+ * clipped to the image; n' counts the in-image members.  m' = S1'/n',
+ * s' = sqrt(sum (f - m')^2 / n') (second pass), t' = m' [1 + k (s'/R' - 1)]
+ * (Eq. 5, R' the caller's dynamic range of s'), and g = 0 if f < t' (Eq. 3).
+ * Every output pointer except out may be NULL.
+ */
+static int gs_member(int structure, int dy, int dx) {
+    switch (structure) {
+        case 0: return dy == 0 || dx == 0;
+        case 1: return dy == dx || dy == -dx;
+        case 2: return dy == 0 || dx == 0 || dy == dx || dy == -dx;
+        default: return 0;
+    }
+}
+
+int oracle_binarize_gs(const uint8_t *img, int H, int W, int channels, int win, double k,
+                       double Rp, int structure, uint32_t *s1, uint32_t *s2, uint32_t *n,
+                       double *t, uint8_t *out) {
+    if (!img || !out || H < 1 || W < 1 || (channels != 1 && channels != 3)) return OR_ERR_ARG;
+    if (win < 1 || win > 255 || win % 2 == 0) return OR_ERR_ARG;
+    if (structure < 0 || structure > 2 || !(Rp > 0.0)) return OR_ERR_ARG;
+    const int r = win / 2;
+    /* the members of S' as offsets from the centre */
+    int *dys = (int *)malloc(sizeof(int) * (size_t)win * win);
+    int *dxs = (int *)malloc(sizeof(int) * (size_t)win * win);
+    size_t npx = (size_t)H * (size_t)W;
+    uint8_t *f = (uint8_t *)malloc(npx);
+    if (!dys || !dxs || !f) {
+        free(dys);
+        free(dxs);
+        free(f);
+        return OR_ERR_NOMEM;
+    }
+    int nm = 0;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx)
+            if (gs_member(structure, dy, dx)) {
+                dys[nm] = dy;
+                dxs[nm] = dx;
+                ++nm;
+            }
+    oracle_gray(img, H, W, channels, f);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            uint64_t a = 0, b = 0, cnt = 0;
+            for (int i = 0; i < nm; ++i) {
+                const int yy = y + dys[i], xx = x + dxs[i];
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const uint64_t v = f[(size_t)yy * W + xx];
+                a += v;
+                b += v * v;
+                ++cnt;
+            }
+            const double m = (double)a / (double)cnt;
+            double acc = 0.0;
+            for (int i = 0; i < nm; ++i) {
+                const int yy = y + dys[i], xx = x + dxs[i];
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const double d = (double)f[(size_t)yy * W + xx] - m;
+                acc += d * d;
+            }
+            const double s = sqrt(acc / (double)cnt);
+            const double tt = m * (1.0 + k * (s / Rp - 1.0)); /* Eq. 5 */
+            const size_t i = (size_t)y * W + x;
+            if (s1) s1[i] = (uint32_t)a;
+            if (s2) s2[i] = (uint32_t)b;
+            if (n) n[i] = (uint32_t)cnt;
+            if (t) t[i] = tt;
+            out[i] = ((double)f[i] < tt) ? 0 : 255; /* Eq. 3 */
+        }
+    free(dys);
+    free(dxs);
+    free(f);
+    return OR_OK;
 }
