@@ -40,10 +40,14 @@ DOMINANT = "bz_page_kernel<256, gray, sauvola>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bz_page_kernel_sauvola_gray_4096.json")
 
 
+# the sources the dominant kernel and its launch are built from
+KERNEL_SOURCES = ("binarize.hip", "bz_common.hpp", "bz_tile.hpp")
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1210_3165_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -234,6 +238,42 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int) -> di
     return res
 
 
+def run_otsu_workload(reps: int, pool_mb: int) -> dict:
+    """Otsu's global threshold (histogram, selection, Eq. 2 decision) on the
+    4096^2 gray page and on A4 RGB pages, from a rotating buffer pool."""
+    import torch
+
+    import pagegen
+    import paper_1210_3165_amd as bz
+    dev = torch.device("cuda:0")
+    runs = []
+    for (H, W, C) in [(4096, 4096, 1), (3508, 2480, 3)]:
+        img = torch.from_numpy(pagegen.page(H, W, pagegen.strokes_for(H, W), seed=4000 + C,
+                                            channels=C)).to(dev)
+        n = max(2, math.ceil(pool_mb * 2**20 / (H * W * (C + 1))))
+        ins = [img.clone() for _ in range(n)]
+        outs = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(n)]
+        o = bz.Otsu(dev)
+        for i in range(n):
+            o.run(ins[i], outs[i])
+        torch.cuda.synchronize()
+        res = {"H": H, "W": W, "channels": C, "T": o.T}
+        for mode in ("threshold+decision", "threshold only"):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for r in range(reps):
+                o.run(ins[r % n], outs[r % n], threshold_only=(mode == "threshold only"))
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = H * W * ((2 * C + 1) if mode == "threshold+decision" else C)
+            res[mode] = {"us": ms * 1e3, "gpix_s": H * W / (ms * 1e-3) / 1e9,
+                         "alg_GBps": nbytes / (ms * 1e-3) / 1e9,
+                         "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+        runs.append(res)
+    return {"workload": "otsu", "runs": runs}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,9 +287,10 @@ def main() -> int:
                     help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
-                    choices=["page4096", "batch-rgb", "batch-mixed", "serve"],
+                    choices=["page4096", "batch-rgb", "batch-mixed", "serve", "otsu"],
                     help="page4096: the metric line; batch-*: per-image vs persistent batch; "
-                         "serve: continuous batching vs one launch per request")
+                         "serve: continuous batching vs one launch per request; "
+                         "otsu: the global-threshold baseline")
     ap.add_argument("--rates", default="200,1000,5000", help="serve: Poisson rates, req/s")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds per rate and mode")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent batches (streams)")
@@ -275,6 +316,9 @@ def main() -> int:
     if args.workload == "serve":
         rates = [float(x) for x in args.rates.split(",")]
         print(json.dumps(run_serve_workload(rates, args.duration, args.slots, args.max_batch)), flush=True)
+        return 0
+    if args.workload == "otsu":
+        print(json.dumps(run_otsu_workload(max(10, args.steps), args.pool_mb)), flush=True)
         return 0
     if args.workload != "page4096":
         print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20), args.lds_cap,

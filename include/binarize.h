@@ -186,6 +186,47 @@ int binarize_otsu(const uint8_t *img, int H, int W_img, int channels, uint8_t *o
                   uint32_t *ws, size_t ws_bytes, void *stream);
 size_t binarize_otsu_workspace_size(void);
 
+/*
+ * Sampled-window Sauvola -- the paper's variant (Sec. 2, Eq. 5): mean m' and
+ * deviation s' over a subset S' of O(W) window pixels on a geometric
+ * structure, t' = m' [1 + k (s'/R' - 1)] with R' the dynamic range of s',
+ * out = 0 where f < t', 255 elsewhere (Eq. 3).  The paper's own structures
+ * (its Fig. 1) are not available; these three are this library's, as
+ * offsets (dy, dx) from the centre of an ODD win x win window:
+ *   BZ_GS_PLUS  dy == 0 or dx == 0 (centre row and column, 2 win - 1 px)
+ *   BZ_GS_X     |dy| == |dx|       (both diagonals,        2 win - 1 px)
+ *   BZ_GS_STAR  both               (                       4 win - 3 px)
+ * clipped to the image; n' counts the in-image members.  Sums are exact,
+ * s' = sqrt(n' S2' - S1'^2) / n', t' is evaluated as for binarize (fp32 from
+ * the exact sums, |t' - t'_exact| < 1e-4).
+ *
+ * binarize_gs -- img, out as for binarize; Rp is R'.  s1, s2, n (u32) and
+ *   t (f32) are optional H x W_img verification planes (NULL to skip).
+ *   Errors: BZ_ERR_WINDOW for an even win or one outside [1, 255],
+ *   BZ_ERR_PARAM for an unknown structure, k not finite or Rp not finite and
+ *   > 0, otherwise as for binarize_stats.  No allocation, one launch.
+ */
+#define BZ_GS_PLUS 0
+#define BZ_GS_X 1
+#define BZ_GS_STAR 2
+
+int binarize_gs(const uint8_t *img, int H, int W_img, int channels, int win,
+                float k, float Rp, int structure, uint8_t *out, uint32_t *s1,
+                uint32_t *s2, uint32_t *n, float *t, void *stream);
+
+/*
+ * binarize_fmeasure_counts -- the counts behind the F-measure of Sec. 3
+ * (Eq. 6: FM = 2 R P / (R + P), R = TP / (TP + FN), P = TP / (TP + FP)).
+ * out: device, npx binarized bytes (0 = text, Eq. 3); gt: device, npx
+ * ground-truth bytes (nonzero = text).  counts: device, 3 x u64, 8-byte
+ * aligned, overwritten with TP (out == 0, gt != 0), FP (out == 0, gt == 0)
+ * and FN (out != 0, gt != 0).  Two launches (clear, count); no allocation.
+ * Errors: BZ_ERR_NULL, BZ_ERR_SHAPE (npx outside [1, 2^31)),
+ * BZ_ERR_WORKSPACE (counts misaligned), BZ_ERR_ALIAS, BZ_ERR_HIP.
+ */
+int binarize_fmeasure_counts(const uint8_t *out, const uint8_t *gt, int64_t npx,
+                             unsigned long long *counts, void *stream);
+
 /* LDS bytes one workgroup of the given tile width needs for a window, or
  * BZ_ERR_TILE if that tile cannot hold the window. */
 int binarize_tile_lds(int tile_w, int win);

@@ -19,6 +19,7 @@ import torch
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
     "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu",
+    "binarize_gs", "fmeasure_counts", "GS_PLUS", "GS_X", "GS_STAR",
 ]
 
 SAUVOLA = 0
@@ -347,3 +348,82 @@ def otsu(img: torch.Tensor, out: torch.Tensor | None = None,
     o = Otsu(img.device)
     out = o.run(img, out, stream=stream)
     return out, o.T
+
+
+# ---------------------------------------------------------------------------
+# Sampled-window variant (Sec. 2, Eq. 5) and F-measure counts (Sec. 3)
+# ---------------------------------------------------------------------------
+
+GS_PLUS, GS_X, GS_STAR = 0, 1, 2
+_GS_NAMES = {"plus": GS_PLUS, "x": GS_X, "star": GS_STAR}
+
+
+def _gs_lib() -> ctypes.CDLL:
+    L = lib()
+    if not getattr(L, "_gs_ready", False):
+        vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+        L.binarize_gs.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, vp, vp, vp, vp]
+        L.binarize_gs.restype = i
+        L.binarize_fmeasure_counts.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+        L.binarize_fmeasure_counts.restype = i
+        L._gs_ready = True
+    return L
+
+
+def _structure(s) -> int:
+    if isinstance(s, str):
+        if s.lower() not in _GS_NAMES:
+            raise ValueError(f"unknown structure {s!r} (plus, x, star)")
+        return _GS_NAMES[s.lower()]
+    return int(s)
+
+
+def binarize_gs(img: torch.Tensor, win: int, k: float, Rp: float = 128.0, structure="plus",
+                out: torch.Tensor | None = None, stats: bool = False,
+                stream: torch.cuda.Stream | None = None):
+    """Sampled-window Sauvola over an odd win x win window's plus / x / star
+    structure (this library's structures; Eq. 5 with R' = Rp).  Returns out,
+    or with stats=True a dict with out, s1, s2, n (int32 views of u32) and
+    t (f32)."""
+    H, W, C = _check_image(img)
+    dev = img.device
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != dev or not out.is_contiguous():
+        raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+    planes = {}
+    if stats:
+        for name, dt in (("s1", torch.int32), ("s2", torch.int32), ("n", torch.int32), ("t", torch.float32)):
+            planes[name] = torch.empty((H, W), dtype=dt, device=dev)
+    with torch.cuda.device(dev):
+        s = ctypes.c_void_p(_stream_ptr(stream, dev))
+        rc = _gs_lib().binarize_gs(_ptr(img), H, W, C, int(win), float(k), float(Rp), _structure(structure),
+                                   _ptr(out), _ptr(planes.get("s1")), _ptr(planes.get("s2")),
+                                   _ptr(planes.get("n")), _ptr(planes.get("t")), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_gs")
+    if stats:
+        planes["out"] = out
+        return planes
+    return out
+
+
+def fmeasure_counts(out: torch.Tensor, gt: torch.Tensor, counts: torch.Tensor | None = None,
+                    stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """TP, FP, FN of a binarized page (0 = text) against a ground-truth mask
+    (nonzero = text), counted on the GPU into a 3-element int64 device
+    tensor (enqueued on the stream)."""
+    for name, t in (("out", out), ("gt", gt)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.device.type != "cuda" \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous uint8 CUDA tensor")
+    if out.numel() != gt.numel() or out.device != gt.device:
+        raise ValueError("out and gt must have the same size and device")
+    if counts is None:
+        counts = torch.empty(3, dtype=torch.int64, device=out.device)
+    with torch.cuda.device(out.device):
+        s = ctypes.c_void_p(_stream_ptr(stream, out.device))
+        rc = _gs_lib().binarize_fmeasure_counts(_ptr(out), _ptr(gt), out.numel(), _ptr(counts), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_fmeasure_counts")
+    return counts

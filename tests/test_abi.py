@@ -147,3 +147,45 @@ def test_otsu_workspace_contract(L):
     vp = ctypes.c_void_p
     L.binarize_otsu_workspace_size.restype = ctypes.c_size_t
     assert L.binarize_otsu_workspace_size() == WS
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -1),           # null img
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, None), -1),            # null out
+    ((FAKE_IN, 0, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT), -2),         # H < 1
+    ((FAKE_IN, 16, 16, 4, 15, 0.5, 128.0, 0, FAKE_OUT), -3),        # RGBA
+    ((FAKE_IN, 16, 16, 1, 14, 0.5, 128.0, 0, FAKE_OUT), -4),        # even window
+    ((FAKE_IN, 16, 16, 1, 257, 0.5, 128.0, 0, FAKE_OUT), -4),       # too wide
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 3, FAKE_OUT), -5),        # unknown structure
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, -1.0, 0, FAKE_OUT), -5),         # R' <= 0
+    ((FAKE_IN, 16, 16, 1, 15, float("inf"), 128.0, 0, FAKE_OUT), -5),
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 2, FAKE_IN + 10), -7),    # out inside img
+])
+def test_gs_invalid_arguments(L, args, code):
+    vp = ctypes.c_void_p
+    L.binarize_gs.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    a = [vp(x) if i in (0, 8) else x for i, x in enumerate(args)]
+    assert L.binarize_gs(*a, None, None, None, None, None) == code
+
+
+def test_gs_stats_planes_must_not_alias(L):
+    vp = ctypes.c_void_p
+    base = [vp(FAKE_IN), 16, 16, 1, 15, 0.5, 128.0, 0, vp(FAKE_OUT)]
+    assert L.binarize_gs(*base, vp(FAKE_OUT + 4), None, None, None, None) == -7   # s1 over out
+    assert L.binarize_gs(*base, None, vp(0x30000000), vp(0x30000000 + 1020), None, None) == -7
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, FAKE_IN, 100, FAKE_WS), -1),
+    ((FAKE_OUT, FAKE_IN, 100, None), -1),
+    ((FAKE_OUT, FAKE_IN, 0, FAKE_WS), -2),
+    ((FAKE_OUT, FAKE_IN, 1 << 31, FAKE_WS), -2),
+    ((FAKE_OUT, FAKE_IN, 100, FAKE_WS + 4), -10),    # counts not 8-byte aligned
+    ((FAKE_OUT, FAKE_IN, 100, FAKE_IN + 8), -7),     # counts over gt
+])
+def test_fmeasure_invalid_arguments(L, args, code):
+    vp = ctypes.c_void_p
+    L.binarize_fmeasure_counts.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    a = [vp(x) if i != 2 else x for i, x in enumerate(args)]
+    assert L.binarize_fmeasure_counts(*a, None) == code
