@@ -16,6 +16,8 @@ degraded document scan:
   float page before rounding (interleaved r, g, b).
 
 The stroke mask is the page's ground truth (foreground = stroke pixels).
+For accuracy studies ``degraded_page`` darkens the shading (background 60 to
+230), lightens the ink (30..110) and raises the noise (sigma 12).
 
 Both the HIP path and the CPU oracle consume these pages; this module holds
 no part of the binarization method.
@@ -36,8 +38,11 @@ def rng_for(seed: int) -> np.random.Generator:
 
 
 def page(H: int, W: int, n_strokes: int, seed: int, channels: int = 1,
-         noise_sigma: float = 8.0, return_mask: bool = False):
-    """One synthetic page, uint8 HxW (channels=1) or HxWx3 (channels=3)."""
+         noise_sigma: float = 8.0, return_mask: bool = False,
+         bg: tuple[float, float] = (150.0, 230.0), ink: tuple[float, float] = (20.0, 60.0)):
+    """One synthetic page, uint8 HxW (channels=1) or HxWx3 (channels=3).
+    bg: background levels at the top-left and bottom-right corners (linear
+    ramp along the diagonal); ink: range of the stroke intensities."""
     if H < 1 or W < 1:
         raise ValueError("page must be at least 1x1")
     if channels not in (1, 3):
@@ -46,7 +51,7 @@ def page(H: int, W: int, n_strokes: int, seed: int, channels: int = 1,
     ys = np.arange(H, dtype=np.float32)[:, None]
     xs = np.arange(W, dtype=np.float32)[None, :]
     denom = float(max((W - 1) + (H - 1), 1))
-    img = (150.0 + 80.0 * (xs + ys) / denom).astype(np.float32)
+    img = (float(bg[0]) + (float(bg[1]) - float(bg[0])) * (xs + ys) / denom).astype(np.float32)
     img = np.broadcast_to(img, (H, W)).copy()
     mask = np.zeros((H, W), dtype=bool) if return_mask else None
 
@@ -56,7 +61,7 @@ def page(H: int, W: int, n_strokes: int, seed: int, channels: int = 1,
     length = rng.integers(10, 61, size=n)
     y0 = rng.integers(0, H, size=n)
     x0 = rng.integers(0, W, size=n)
-    val = rng.uniform(20.0, 60.0, size=n).astype(np.float32)
+    val = rng.uniform(float(ink[0]), float(ink[1]), size=n).astype(np.float32)
     for i in range(n):
         h, w = (thick[i], length[i]) if horiz[i] else (length[i], thick[i])
         ya, xa = y0[i], x0[i]
@@ -75,6 +80,16 @@ def page(H: int, W: int, n_strokes: int, seed: int, channels: int = 1,
     if return_mask:
         return out, mask
     return out
+
+
+DEGRADED = {"bg": (60.0, 230.0), "ink": (30.0, 110.0), "noise_sigma": 12.0}
+
+
+def degraded_page(H: int, W: int, seed: int, channels: int = 1, return_mask: bool = True):
+    """A harder page for accuracy studies: strong shading (background 60 to
+    230 along the diagonal), fainter ink (30..110) and more noise (sigma 12),
+    so that no single global threshold separates ink from paper everywhere."""
+    return page(H, W, strokes_for(H, W), seed, channels, return_mask=return_mask, **DEGRADED)
 
 
 def strokes_for(H: int, W: int) -> int:
