@@ -18,7 +18,6 @@ Prints ONE JSON line (rank 0):
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -40,18 +39,7 @@ DOMINANT = "bz_page_kernel<256, gray, sauvola>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bz_page_kernel_sauvola_gray_4096.json")
 
 
-# the sources the dominant kernel and its launch are built from
-KERNEL_SOURCES = ("binarize.hip", "bz_common.hpp", "bz_tile.hpp")
-
-
-def kernel_source_sha() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1210_3165_amd", "csrc")
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()
+from paper_1210_3165_amd.build import kernel_source_sha  # noqa: E402
 
 
 def measured_traffic():
@@ -274,6 +262,38 @@ def run_otsu_workload(reps: int, pool_mb: int) -> dict:
     return {"workload": "otsu", "runs": runs}
 
 
+def run_gs_workload(reps: int) -> dict:
+    """Exact Sauvola against the sampled-window variant (plus, x, star) on the
+    4096^2 gray page, per window: microseconds per launch from HIP events."""
+    import torch
+
+    import pagegen
+    import paper_1210_3165_amd as bz
+    dev = torch.device("cuda:0")
+    S = 4096
+    img = torch.from_numpy(pagegen.config1(size=S)[0].img).to(dev)
+    out = torch.empty((S, S), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    rows = []
+    for win in (15, 31, 61, 101):
+        row = {"win": win, "exact_us": timed(lambda: bz.binarize(img, win, 0.5, 128.0, out=out))}
+        for name in ("plus", "x", "star"):
+            row[f"{name}_us"] = timed(lambda: bz.binarize_gs(img, win, 0.5, 128.0, name, out=out))
+        rows.append(row)
+    return {"workload": "gs", "H": S, "W": S, "reps": reps, "runs": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,10 +307,10 @@ def main() -> int:
                     help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
-                    choices=["page4096", "batch-rgb", "batch-mixed", "serve", "otsu"],
+                    choices=["page4096", "batch-rgb", "batch-mixed", "serve", "otsu", "gs"],
                     help="page4096: the metric line; batch-*: per-image vs persistent batch; "
                          "serve: continuous batching vs one launch per request; "
-                         "otsu: the global-threshold baseline")
+                         "otsu: the global-threshold baseline; gs: exact vs sampled window")
     ap.add_argument("--rates", default="200,1000,5000", help="serve: Poisson rates, req/s")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds per rate and mode")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent batches (streams)")
@@ -316,6 +336,9 @@ def main() -> int:
     if args.workload == "serve":
         rates = [float(x) for x in args.rates.split(",")]
         print(json.dumps(run_serve_workload(rates, args.duration, args.slots, args.max_batch)), flush=True)
+        return 0
+    if args.workload == "gs":
+        print(json.dumps(run_gs_workload(max(5, args.steps // 20))), flush=True)
         return 0
     if args.workload == "otsu":
         print(json.dumps(run_otsu_workload(max(10, args.steps), args.pool_mb)), flush=True)

@@ -41,6 +41,22 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+# sources of the full-window tile kernel and its single-page launch
+KERNEL_SOURCES = ("binarize.hip", "bz_common.hpp", "bz_tile.hpp")
+
+
+def kernel_source_sha(files=KERNEL_SOURCES) -> str:
+    """SHA-256 over the named csrc files (name and bytes, in the given order):
+    identifies the kernel source a recorded profile was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     """Compile every HIP source into libbinarize.so; returns its path."""
     tmp = LIB + ".tmp"

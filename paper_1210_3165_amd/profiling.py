@@ -1,0 +1,160 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    # kernel-trace summary (markdown) of a `rocprofv3 --kernel-trace --stats
+    # --output-format csv -d DIR -o PREFIX -- <command>` run
+    python -m paper_1210_3165_amd.profiling trace DIR PREFIX --title T --command C
+
+    # HBM traffic per dispatch from two counter runs (FETCH_SIZE, WRITE_SIZE),
+    # scaled by what the same counters read for the plain device copy that ran
+    # in the same process (16 MiB each way)
+    python -m paper_1210_3165_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel SUBSTR ...
+
+Only reads CSV files; runs nothing on the GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import statistics
+import sys
+from collections import defaultdict
+
+from .build import kernel_source_sha
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").replace("void ", "")
+
+
+def trace_summary(d: str, prefix: str, title: str, command: str, note: str = "",
+                  only: tuple[str, ...] = ("bz_", "otsu_", "__amd_rocclr_copyBuffer")) -> str:
+    stats = _rows(f"{d}/{prefix}_kernel_stats.csv")
+    trace = _rows(f"{d}/{prefix}_kernel_trace.csv")
+    out = [f"# {title}", "", "Command (repository root, one MI355X):", "", f"    {command}", ""]
+    if note:
+        out += [note, ""]
+    out += ["## kernel_stats.csv (this library's kernels and the device copy)", "", "| Kernel | Calls | Average ns | Min ns | Max ns | % |",
+            "|---|---|---|---|---|---|"]
+    for r in stats:
+        if not any(o in r["Name"] for o in only):
+            continue
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | "
+                   f"{r['MaxNs']} | {float(r['Percentage']):.1f} |")
+    groups = defaultdict(list)
+    meta = {}
+    for r in trace:
+        if not any(o in r["Kernel_Name"] for o in only):
+            continue
+        key = (_short(r["Kernel_Name"]).split("(")[0], int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        groups[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        meta[key] = (r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
+    out += ["", "## per launch shape (kernel_trace.csv)", "",
+            "| Kernel | grid threads | workgroup | LDS bytes | VGPR | SGPR | launches | mean us | median us |",
+            "|---|---|---|---|---|---|---|---|---|"]
+    per_name = defaultdict(list)
+    for key in groups:
+        per_name[key[0]].append(key)
+    for name in sorted(per_name):
+        keys = sorted(per_name[name], key=lambda k: -k[1])
+        if len(keys) > 8:  # many launch shapes (uneven pages): one aggregate row
+            v = [x for k in keys for x in groups[k]]
+            lds, vg, sg = meta[keys[0]]
+            out.append(f"| `{name}` | {len(keys)} shapes, {min(k[1] for k in keys)}..{max(k[1] for k in keys)} | "
+                       f"{keys[0][2]} | {lds} | {vg} | {sg} | {len(v)} | {statistics.mean(v):.1f} | "
+                       f"{statistics.median(v):.1f} |")
+            continue
+        for key in keys:
+            v = groups[key]
+            lds, vg, sg = meta[key]
+            out.append(f"| `{key[0]}` | {key[1]} | {key[2]} | {lds} | {vg} | {sg} | {len(v)} | "
+                       f"{statistics.mean(v):.1f} | {statistics.median(v):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter(path, counter):
+    per = defaultdict(list)
+    for r in _rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        per[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return per
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, workload: str,
+            commands: list[str], sources: tuple[str, ...]) -> dict:
+    fetch = _counter(fetch_csv, "FETCH_SIZE")
+    write = _counter(write_csv, "WRITE_SIZE")
+
+    def pick(per, sub):
+        vals, grids = [], {}
+        name = None
+        for (n, g), v in per.items():
+            if sub in n:
+                vals += v
+                grids.setdefault(g, []).extend(v)
+                name = n
+        return name, vals, grids
+
+    cf = [v for (n, _), vs in fetch.items() if n == COPY_KERNEL for v in vs]
+    cw = [v for (n, _), vs in write.items() if n == COPY_KERNEL for v in vs]
+    name, kf, grids = pick(fetch, kernel)
+    _, kw, _ = pick(write, kernel)
+    if not (cf and cw and kf and kw):
+        raise SystemExit("missing copy or kernel dispatches in the counter files")
+    copy_kib = copy_bytes / 1024
+    fs, ws = copy_kib / statistics.median(cf), copy_kib / statistics.median(cw)
+    f_raw, w_raw = statistics.mean(kf), statistics.mean(kw)
+    return {
+        "kernel": name,
+        "workload": workload,
+        "source_sha": kernel_source_sha(sources),
+        "fetch_kib_per_dispatch_raw": round(f_raw, 1),
+        "write_kib_per_dispatch_raw": round(w_raw, 1),
+        "copy_fetch_kib_raw": round(statistics.median(cf), 1),
+        "copy_write_kib_raw": round(statistics.median(cw), 1),
+        "copy_bytes_each_way": copy_bytes,
+        "fetch_scale": round(fs, 4),
+        "write_scale": round(ws, 4),
+        "bytes_per_launch": int(round((f_raw * fs + w_raw * ws) * 1024)),
+        "per_grid_fetch_kib_raw": {str(g): round(statistics.mean(v), 1) for g, v in sorted(grids.items())},
+        "commands": commands,
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("prefix")
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--note", default="")
+    f = sub.add_parser("traffic")
+    f.add_argument("fetch_csv")
+    f.add_argument("write_csv")
+    f.add_argument("--kernel", required=True, help="substring of the kernel name")
+    f.add_argument("--copy-bytes", type=int, default=16 * 2**20)
+    f.add_argument("--workload", required=True)
+    f.add_argument("--command", action="append", default=[])
+    f.add_argument("--sources", default="binarize.hip,bz_common.hpp,bz_tile.hpp")
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        sys.stdout.write(trace_summary(a.dir, a.prefix, a.title, a.command, a.note))
+    else:
+        rec = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.workload, a.command,
+                      tuple(a.sources.split(",")))
+        sys.stdout.write(json.dumps(rec, indent=1) + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
