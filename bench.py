@@ -183,45 +183,59 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
     return res
 
 
-def run_serve_workload(rates, duration: float, slots: int, max_pages: int) -> dict:
-    """Poisson request streams served twice on the same device-resident
-    inputs: continuous batching (persistent batched launches on `slots`
-    streams) and the plain form (one launch per request)."""
+def run_serve_workload(rates, duration: float, slots: int, max_pages: int, payload: str = "device") -> dict:
+    """Poisson request streams served on the same inputs in several modes:
+    device-resident payloads with continuous batching (persistent batched
+    launches on `slots` streams) and in the plain form (one launch per
+    request); host-origin payloads (pinned host in and out, copies on the
+    slots' streams) batched and one request per batch."""
     import torch
 
     import pagegen
-    from paper_1210_3165_amd.serve import (GpuBatchExecutor, GpuSingleExecutor, Request, Server,
-                                           WallClock)
+    from paper_1210_3165_amd.serve import (GpuBatchExecutor, GpuHostBatchExecutor, GpuSingleExecutor,
+                                           Request, Server, WallClock)
     dev = torch.device("cuda:0")
-    canv = pagegen.device_canvases(dev)
+    canv = {"device": pagegen.device_canvases(dev)}
+    if payload in ("host", "both"):
+        canv["host"] = pagegen.pinned_canvases()
     free, _ = torch.cuda.mem_get_info(dev)
     budget = int(min(free * 0.5, 32 << 30))
+    modes = {"device": ["batched", "single"], "host": ["host-batched", "host-single"],
+             "both": ["batched", "single", "host-batched", "host-single"]}[payload]
 
-    def requests(rate, seed):
+    def requests(rate, seed, where):
         rng = np.random.default_rng(seed)
         out = []
         for i, (t, H, W, C, win, k) in enumerate(pagegen.config4_stream(rate, duration, seed)):
             r = Request(i, t, H, W, C, win, k)
-            r.img = pagegen.canvas_view(canv, H, W, C, rng)
+            r.img = pagegen.canvas_view(canv[where], H, W, C, rng)
             out.append(r)
         return out
 
     def serve(mode, reqs):
-        ex = GpuBatchExecutor(slots, max_pages) if mode == "batched" else GpuSingleExecutor(slots)
+        if mode == "batched":
+            ex, mp = GpuBatchExecutor(slots, max_pages), max_pages
+        elif mode == "single":
+            ex, mp = GpuSingleExecutor(slots), 1
+        else:
+            ex, mp = GpuHostBatchExecutor(slots, max_pages), (max_pages if mode == "host-batched" else 1)
         clock = WallClock()
         ex.start(clock)
-        st = Server(ex, budget, max_batch_pages=max_pages if mode == "batched" else 1).run(reqs, clock)
+        st = Server(ex, budget, max_batch_pages=mp).run(reqs, clock)
         torch.cuda.synchronize()
         ex.close()
-        return st.summary()
+        s = st.summary()
+        span = max(r.done for r in st.completed) - min(r.arrival for r in st.completed)
+        s["payload_GBps"] = sum(r.footprint for r in st.completed) / span / 1e9 if span > 0 else 0.0
+        return s
 
-    serve("batched", requests(1000.0, 1)[:100])  # warm-up (kernels loaded, pools filled)
-    serve("single", requests(1000.0, 1)[:100])
+    for mode in modes:  # warm-up (kernels loaded, pools filled)
+        serve(mode, requests(1000.0, 1, "host" if mode.startswith("host") else "device")[:100])
     res = {"workload": "serve", "duration_s": duration, "slots": slots, "max_batch_pages": max_pages,
-           "hbm_budget_GB": budget / 1e9, "runs": []}
+           "hbm_budget_GB": budget / 1e9, "payload": payload, "runs": []}
     for rate in rates:
-        for mode in ("batched", "single"):
-            s = serve(mode, requests(rate, 5000 + int(rate)))
+        for mode in modes:
+            s = serve(mode, requests(rate, 5000 + int(rate), "host" if mode.startswith("host") else "device"))
             res["runs"].append({"rate": rate, "mode": mode, **s})
     return res
 
@@ -315,6 +329,8 @@ def main() -> int:
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds per rate and mode")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent batches (streams)")
     ap.add_argument("--max-batch", type=int, default=32, help="serve: pages per micro-batch")
+    ap.add_argument("--payload", default="device", choices=["device", "host", "both"],
+                    help="serve: device-resident inputs, pinned host inputs/outputs, or both")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -335,7 +351,8 @@ def main() -> int:
     bz.lib()
     if args.workload == "serve":
         rates = [float(x) for x in args.rates.split(",")]
-        print(json.dumps(run_serve_workload(rates, args.duration, args.slots, args.max_batch)), flush=True)
+        print(json.dumps(run_serve_workload(rates, args.duration, args.slots, args.max_batch, args.payload)),
+              flush=True)
         return 0
     if args.workload == "gs":
         print(json.dumps(run_gs_workload(max(5, args.steps // 20))), flush=True)

@@ -206,6 +206,19 @@ def device_canvases(device):
                                      channels=C).reshape(-1)).to(device) for C in (1, 3)}
 
 
+def pinned_canvases():
+    """The same two canvases in pinned host memory (host-origin requests)."""
+    import torch
+    out = {}
+    for C in (1, 3):
+        src = torch.from_numpy(page(4096, 4096, strokes_for(4096, 4096), seed=4000 + C,
+                                    channels=C).reshape(-1))
+        dst = torch.empty(src.numel(), dtype=torch.uint8, pin_memory=True)
+        dst.copy_(src)
+        out[C] = dst
+    return out
+
+
 def canvas_view(canvases, H: int, W: int, C: int, rng: np.random.Generator):
     n = H * W * C
     base = canvases[C]

@@ -18,8 +18,11 @@ server:
 
 Executors: ``GpuBatchExecutor`` (one persistent-launch batch object and one
 stream per slot), ``GpuSingleExecutor`` (the plain one-launch-per-request
-form, for comparison) and ``FakeExecutor`` (simulated time, used to test the
-scheduler on the CPU).
+form, for comparison), ``GpuHostBatchExecutor`` (host-origin payloads: the
+slot's stream copies pinned host pages in, binarizes and copies the results
+back to pinned host buffers, so copies of one slot overlap kernels of
+another) and ``FakeExecutor`` (simulated time, used to test the scheduler on
+the CPU).
 """
 from __future__ import annotations
 
@@ -261,6 +264,28 @@ class _BufferPool:
         self.free.setdefault(buf.numel(), []).append(buf)
 
 
+class _PinnedPool:
+    """Pinned host buffers in power-of-two size classes (allocated new with
+    pin_memory, reused after the batch that used them retires)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.free = {}
+        self.bytes = 0
+
+    def get(self, n: int):
+        cls = 1 << max(12, (n - 1).bit_length())
+        lst = self.free.setdefault(cls, [])
+        if lst:
+            return lst.pop()
+        self.bytes += cls
+        return self.torch.empty(cls, dtype=self.torch.uint8, pin_memory=True)
+
+    def put(self, buf):
+        self.free.setdefault(buf.numel(), []).append(buf)
+
+
 class _GpuBase:
     def __init__(self, slots: int, device=None):
         import torch
@@ -350,3 +375,52 @@ class GpuSingleExecutor(_GpuBase):
 
     def close(self):
         pass
+
+
+class GpuHostBatchExecutor(GpuBatchExecutor):
+    """Host-origin payloads: ``r.img`` is a pinned host tensor (HxW or HxWx3
+    uint8).  Per micro-batch, on the slot's stream: copy every page in (H2D),
+    binarize (plain launch for one page, persistent batch otherwise), copy
+    every result out (D2H) into a pinned host buffer that becomes ``r.out``.
+    A request completes when its result is in host memory."""
+
+    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None):
+        super().__init__(slots, max_pages, lds_cap, device)
+        self.host_pool = _PinnedPool()
+        self.host_bufs = {}
+
+    def submit(self, slot, batch, now):
+        torch = self.torch
+        st = self.streams[slot]
+        dev_bufs, host_bufs, jobs = [], [], []
+        with torch.cuda.stream(st):
+            for r in batch:
+                shape = (r.H, r.W) if r.C == 1 else (r.H, r.W, 3)
+                n_in = r.pixels * r.C
+                bi = self.pool.get(n_in)
+                bo = self.pool.get(r.pixels)
+                dev_bufs += [bi, bo]
+                din = bi[:n_in].view(shape)
+                din.copy_(r.img, non_blocking=True)
+                jobs.append((din, bo[:r.pixels].view(r.H, r.W), r))
+            if len(jobs) == 1:
+                from . import binarize
+                din, dout, r = jobs[0]
+                binarize(din, r.win, r.k, r.R, r.rule, out=dout, stream=st)
+            else:
+                self.batches[slot].run([(din, dout, r.win, r.k, r.R, r.rule) for din, dout, r in jobs],
+                                       use_graph=False, stream=st)
+            for din, dout, r in jobs:
+                hb = self.host_pool.get(r.pixels)
+                host_bufs.append(hb)
+                hout = hb[:r.pixels].view(r.H, r.W)
+                hout.copy_(dout, non_blocking=True)
+                r.out = hout
+        self.bufs[slot] = dev_bufs
+        self.host_bufs[slot] = host_bufs
+        self._finish(slot)
+
+    def release(self, slot):
+        super().release(slot)
+        for b in self.host_bufs.pop(slot, []):
+            self.host_pool.put(b)

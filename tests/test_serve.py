@@ -98,3 +98,42 @@ def test_gpu_served_mix_equals_pages_alone():
         alone = bz.binarize(r.img, r.win, r.k, r.R, r.rule)
         assert torch.equal(alone, outs[r.rid]), r.rid
     ex.close()
+
+
+@pytest.mark.gpu
+def test_gpu_host_payloads_equal_pages_alone():
+    """Host-origin requests (pinned host in, pinned host out) in bursty mixes:
+    every result equals the page binarized alone on the device."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import pagegen
+    import paper_1210_3165_amd as bz
+    from paper_1210_3165_amd.serve import GpuHostBatchExecutor, WallClock
+    canv = pagegen.pinned_canvases()
+    rng = np.random.default_rng(5)
+    rs = []
+    for i, (t, H, W, C, win, k) in enumerate(pagegen.config4_stream(2000.0, 0.04, seed=6)):
+        H, W = min(H, 1200), min(W, 1200)
+        r = Request(i, (i // 5) * 2e-3, H, W, C, win, k, rule=i % 2)
+        r.img = pagegen.canvas_view(canv, H, W, C, rng)
+        assert r.img.is_pinned()
+        rs.append(r)
+    assert len(rs) > 30
+    ex = GpuHostBatchExecutor(slots=3, max_pages=8)
+    clock = WallClock()
+    ex.start(clock)
+    outs = {}
+
+    def keep(r):
+        assert r.out.device.type == "cpu"
+        outs[r.rid] = r.out.clone()
+
+    st = Server(ex, hbm_budget=256 << 20, max_batch_pages=8).run(rs, clock, on_done=keep)
+    torch.cuda.synchronize()
+    assert len(st.completed) == len(rs) and not st.refused
+    assert max(st.batch_sizes) > 1
+    for r in rs:
+        alone = bz.binarize(r.img.cuda(), r.win, r.k, r.R, r.rule).cpu()
+        assert torch.equal(alone, outs[r.rid]), r.rid
+    ex.close()
