@@ -95,7 +95,7 @@ int make_plan(int H, int W, int win, int tile_w, int tile_h, Plan *p) {
     return BZ_OK;
 }
 
-void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int win, float k, float R,
+void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int C, int win, float k, float R,
                uint8_t *out, const Plan &p) {
     a->img = img;
     a->out = out;
@@ -115,6 +115,7 @@ void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int win, float k, 
     a->n_tiles = p.tiles_x * p.tiles_y;
     a->rp = ring_pitch(p.tile_w, win);
     a->depth = ring_depth(win);
+    a->row_aligned = (((uintptr_t)img & 15) == 0 && ((int64_t)W * C) % 16 == 0) ? 1 : 0;
 }
 
 template <int TW, int C, int RULE, bool STATS>
@@ -177,7 +178,7 @@ int run(const uint8_t *img, int H, int W, int C, int win, float k, float R, int 
     // Niblack form decides ties in exact integers.
     if (rule == BZ_SAUVOLA && k == 0.0f) rule = BZ_NIBLACK;
     PageArgs a;
-    fill_args(&a, img, H, W, win, k, R, out, p);
+    fill_args(&a, img, H, W, C, win, k, R, out, p);
     if (stats) {
         a.gray = gray;
         a.s1 = s1;

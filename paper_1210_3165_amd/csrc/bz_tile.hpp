@@ -72,9 +72,22 @@ struct RawChunk {
 // edge (clamp == true) every word address is clamped into the words that hold
 // at least one byte of this row, so no access leaves the caller's buffer.
 // Bytes that belong to columns outside [0, W) are discarded by chunk_gray.
-template <int C>
+template <int C, bool AL>
 __device__ __forceinline__ void fetch_chunk(RawChunk<C> &k, const uint8_t *__restrict__ rowp, int xs, int W,
                                             bool clamp) {
+    if (AL) {  // 16-byte aligned chunk, wholly inside the row: C vector loads
+        const uint4 *q = reinterpret_cast<const uint4 *>(rowp + C * xs);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const uint4 v = q[i];
+            k.w[4 * i] = v.x;
+            k.w[4 * i + 1] = v.y;
+            k.w[4 * i + 2] = v.z;
+            k.w[4 * i + 3] = v.w;
+        }
+        k.sh = 0;
+        return;
+    }
     const uintptr_t ad = (uintptr_t)rowp + (uintptr_t)(intptr_t)(C * xs);
     k.sh = (uint32_t)(ad & 3);
     uintptr_t q = ad - k.sh;
@@ -94,12 +107,12 @@ __device__ __forceinline__ void fetch_chunk(RawChunk<C> &k, const uint8_t *__res
 }
 
 // 16 gray levels from a fetched chunk; columns outside [0, W) become 0.
-template <int C>
+template <int C, bool AL>
 __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W, bool clamp) {
     constexpr int NB = C == 1 ? 4 : 12;
     uint32_t b[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) b[i] = align_bytes(k.w[i + 1], k.w[i], k.sh);
+    for (int i = 0; i < NB; ++i) b[i] = AL ? k.w[i] : align_bytes(k.w[i + 1], k.w[i], k.sh);
     uint32_t o[4];
     if (C == 1) {
 #pragma unroll
@@ -112,7 +125,7 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
             o[px >> 2] |= gray_of(byte_at(b, 3 * px), byte_at(b, 3 * px + 1), byte_at(b, 3 * px + 2))
                           << (8 * (px & 3));
     }
-    if (clamp) {
+    if (!AL && clamp) {
 #pragma unroll
         for (int px = 0; px < 16; ++px) {
             const int c = xs + px;
@@ -125,8 +138,10 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
 // The job of this thread for a block of up to RB rows: row i = job / nq of
 // the block, chunk q = job % nq (nq = rp / 16 chunks per row).  RB * rp / 16
 // <= 256 gives at most one job per thread.  Rows outside the image load a clamped
-// row (always a valid address) and store zeros.
-template <int C>
+// row (always a valid address) and store zeros.  INT: an interior tile (every
+// staged row and column lies inside the image, rows 16-byte aligned), which
+// needs no clamping, no masking and loads whole 16-byte chunks.
+template <int C, bool INT>
 struct Stager {
     RawChunk<C> k;
     int job_row, job_q;  // job_row >= kRowsPerStep: this thread has no job
@@ -136,14 +151,19 @@ struct Stager {
         const int nq = a.rp >> 4;
         job_row = (int)threadIdx.x / nq;
         job_q = (int)threadIdx.x - job_row * nq;
+        in_image = true;
     }
 
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
         if (job_row < nrows) {
             const int row = row0 + job_row;
-            in_image = row >= 0 && row < a.H;
-            const int rc = min(max(row, 0), a.H - 1);
-            fetch_chunk<C>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
+            if (INT) {
+                fetch_chunk<C, true>(k, a.img + (size_t)row * (size_t)a.W * C, xr0 + 16 * job_q, a.W, false);
+            } else {
+                in_image = row >= 0 && row < a.H;
+                const int rc = min(max(row, 0), a.H - 1);
+                fetch_chunk<C, false>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
+            }
         }
     }
 
@@ -152,8 +172,8 @@ struct Stager {
         if (job_row >= nrows) return;
         int sl = slot0 + job_row;
         if (sl >= a.depth) sl -= a.depth;
-        uint4 v = chunk_gray<C>(k, xr0 + 16 * job_q, a.W, clamp);
-        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
+        uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
+        if (!INT && !in_image) v = make_uint4(0u, 0u, 0u, 0u);
         *(uint4 *)(ring + sl * a.rp + 16 * job_q) = v;
     }
 };
@@ -324,7 +344,7 @@ __device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, u
     }
 }
 
-template <int TW, int C, int RULE, bool STATS>
+template <int TW, int C, int RULE, bool STATS, bool INT>
 __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_t *smem) {
     constexpr int RB = kRowsPerStep;
     constexpr int TPR = kThreadsPerRow;
@@ -352,10 +372,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
     // extra word a chunk may read past its last byte all lie inside the row.
-    const bool clamp = xr0 < 0 || xr0 + rp + 4 > a.W;
+    const bool clamp = !INT && (xr0 < 0 || xr0 + rp + 4 > a.W);
 
     // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1
-    Stager<C> pre;  // rows of the next step, in flight while this one computes
+    Stager<C, INT> pre;  // rows of the next step, in flight while this one computes
     pre.init(a);
     for (int r0 = 0; r0 < win; r0 += RB) {
         const int nr = min(RB, win - r0);
@@ -399,7 +419,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
-    const bool x_inside = X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1;
+    const bool x_inside = INT || (X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1);
+    // interior tiles: every window is whole, n = win^2 on every row
+    const uint32_t n_full = (uint32_t)__mul24(win, win);
+    const RowSauvola q_full = row_sauvola(a, n_full);
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
@@ -446,19 +469,18 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         load_u16<OPT>(Vb1 + hr * vbw + hs * OPT, B1);
         load_v2<OPT>(Va2 + hr * TW, TW, hs, A2);
         load_v2<OPT>(Vb2 + hr * vbw, vbw, hs, B2);
-        // starting value: window sum one column left of the tile.  Every read
-        // stays inside the LDS allocation (rows are vbw >= 32 * ceil(win / 32)
-        // wide, and the last Vb2 row is followed by the trash slot and the
-        // ring of the next row); entries at i >= win are masked after the read.
+        // starting value: window sum one column left of the tile (entries
+        // 0 .. win-1 of the Vb row).  A uniform, not unrolled loop over
+        // 32-entry blocks: reads stay below 32 * ceil(win / 32) <= vbw, and
+        // entries at i >= win are masked after the read.
         uint32_t h1 = 0, h2 = 0;
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {  // win <= 255 < 8 * 32
-            if (it * TPR < win) {         // uniform
-                const int i = hs + it * TPR;
-                const uint32_t x1 = Vb1[hr * vbw + i], x2 = Vb2[hr * vbw + v2_pos(i, vbw)];
-                h1 += i < win ? x1 : 0u;
-                h2 += i < win ? x2 : 0u;
-            }
+        const int nblk = (win + TPR - 1) / TPR;
+#pragma unroll 1
+        for (int it = 0; it < nblk; ++it) {
+            const int i = hs + it * TPR;
+            const uint32_t x1 = Vb1[hr * vbw + i], x2 = Vb2[hr * vbw + v2_pos(i, vbw)];
+            h1 += i < win ? x1 : 0u;
+            h2 += i < win ? x2 : 0u;
         }
         // running sums of the entering-minus-leaving columns
         uint32_t E1[OPT], E2[OPT];
@@ -485,16 +507,16 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) fw[i] = align_bytes(fq[i + 1], fq[i], fsh);
 
-        const int ny = min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
+        const int ny = INT ? win : min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
         const int xs = X0 + hs * OPT;
         uint32_t ow[OPT / 4];
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float sqv[OPT];
         if (x_inside) {  // n = win * ny for the whole row segment
-            const uint32_t n = (uint32_t)__mul24(win, ny);
+            const uint32_t n = INT ? n_full : (uint32_t)__mul24(win, ny);
             if (RULE == 0) {
-                const RowSauvola q = row_sauvola(a, n);
+                const RowSauvola q = INT ? q_full : row_sauvola(a, n);
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
                     const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
@@ -541,11 +563,30 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 }
 
+// Interior tiles take a specialised body: every staged row and column lies
+// inside the image and rows are 16-byte aligned, so staging needs no clamping
+// or masking and loads whole 16-byte chunks, and every window is whole
+// (n = win^2), so the Sauvola row constants are computed once per tile.  The
+// choice is uniform per workgroup; both bodies produce identical bytes.
+template <int TW, int C, int RULE, bool STATS>
+__device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int X0 = tx * TW, Y0 = ty * a.tile_h;
+    const int xr0 = floor16(X0 - a.lo - 1);
+    const bool interior = a.row_aligned && xr0 >= 0 && xr0 + a.rp + 4 <= a.W && X0 - a.lo >= 0 &&
+                          X0 + TW - 1 + a.hi <= a.W - 1 && Y0 - a.lo - 1 >= 0 &&
+                          Y0 + a.tile_h - 1 + a.hi <= a.H - 1;
+    if (interior)
+        process_tile<TW, C, RULE, STATS, true>(a, tile, smem);
+    else
+        process_tile<TW, C, RULE, STATS, false>(a, tile, smem);
+}
+
 template <int TW, int C, int RULE, bool STATS>
 __global__ void __launch_bounds__(kThreads, 4) bz_page_kernel(PageArgs a) {
     extern __shared__ uint4 bz_lds[];
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    process_tile<TW, C, RULE, STATS>(a, tile, (uint8_t *)bz_lds);
+    run_tile<TW, C, RULE, STATS>(a, tile, (uint8_t *)bz_lds);
 }
 
 }  // namespace bz

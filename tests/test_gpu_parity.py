@@ -209,6 +209,32 @@ def test_unaligned_buffers(bz, oracle_mod, offset):
         assert int(obuf[:offset + 3].sum()) == 0 and int(obuf[offset + 3 + H * W:].sum()) == 0
 
 
+@pytest.mark.parametrize("C,rule,win,k", [(1, 0, 15, 0.5), (1, 0, 31, 0.34), (1, 1, 31, -0.2), (1, 0, 61, 0.5),
+                                          (3, 0, 31, 0.34), (3, 1, 15, -0.2), (1, 0, 101, 0.5)])
+def test_interior_tiles_full_compare(bz, oracle_mod, C, rule, win, k):
+    """A page large enough for interior tiles (whole windows, no clamping,
+    16-byte aligned rows: the specialised tile body), compared pixel by pixel
+    with the oracle; the same page one byte off alignment (general body only)
+    gives identical bytes."""
+    import pagegen
+    from oracle.compare import compare_stats
+    H, W = 700, 1104  # W * C is a multiple of 16
+    img = pagegen.page(H, W, pagegen.strokes_for(H, W), seed=900 + win + C, channels=C)
+    k = f32(k)
+    ref = oracle_mod.binarize(img, win, k, 128.0, rule)
+    g = gpu_stats(bz, img, win, k, 128.0, rule)
+    rep = compare_stats(g, ref)
+    assert rep["ok"], rep
+    aligned = gpu_out(bz, img, win, k, 128.0, rule)
+    assert np.array_equal(aligned, g["out"])
+    buf = torch.zeros(img.size + 16, dtype=torch.uint8, device="cuda")
+    shifted = buf[1:1 + img.size].view(*img.shape)
+    shifted.copy_(torch.from_numpy(img))
+    out = bz.binarize(shifted, win, k, 128.0, rule)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), aligned)
+
+
 # ------------------------------------------------------------ full size, sampled
 
 def sample_points(H, W, win, n, seed):
