@@ -60,13 +60,17 @@ BZ_HD inline int ring_bytes(int tile_w, int win) {
 }
 // Width of the Vb rows: the tile, or the whole first window if that is wider.
 BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
-// LDS layout: ring | Va1 [RB][TW] u16 | Vb1 [RB][vbw] u16 | Va2 [RB][TW] u32 |
-// Vb2 [RB][vbw] u32 | trash [4][kThreads] u32 (per-thread targets of the writes
-// that fall outside Va / Vb, so the vertical pass needs no branches and no two
-// lanes write the same address)
+// Row pitches of the V arrays: the entries a row needs, then 32 trash entries
+// that take the writes of the columns the row does not need, so every column
+// writes at one fixed offset per row (lanes of a wave share a trash entry at
+// most in pairs).  For 256-column tiles vb_width is always 256.
+BZ_HD inline int va_pitch(int tile_w) { return tile_w + 32; }
+BZ_HD inline int vb_pitch(int tile_w, int win) { return vb_width(tile_w, win) + 32; }
+// LDS layout: ring | Va1 [RB][va_pitch] u16 | Vb1 [RB][vb_pitch] u16 |
+// Va2 [RB][va_pitch] u32 | Vb2 [RB][vb_pitch] u32
 BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
-    const int w = vb_width(tile_w, win);
-    return ring_bytes(tile_w, win) + kRowsPerStep * (tile_w * 2 + w * 2 + tile_w * 4 + w * 4) + kThreads * 16;
+    const int pa = va_pitch(tile_w), pb = vb_pitch(tile_w, win);
+    return ring_bytes(tile_w, win) + kRowsPerStep * (pa * 2 + pb * 2 + pa * 4 + pb * 4);
 }
 
 // Position of entry x in a V2 row of `width` entries.  Thread h of a row group

@@ -52,6 +52,32 @@ __device__ __forceinline__ uint32_t byte_at(const uint32_t (&w)[N], int i) {
     return (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
 }
 
+// Difference and sum of byte B of two words, each one VALU instruction with
+// byte-select operands (plain arithmetic instructions, no memory access).
+template <int B>
+__device__ __forceinline__ int byte_sub(uint32_t x, uint32_t y) {
+    int d;
+    if (B == 0)
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0"
+            : "=v"(d) : "v"(x), "v"(y));
+    else
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1"
+            : "=v"(d) : "v"(x), "v"(y));
+    return d;
+}
+
+template <int B>
+__device__ __forceinline__ int byte_add(uint32_t x, uint32_t y) {
+    int d;
+    if (B == 0)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0"
+            : "=v"(d) : "v"(x), "v"(y));
+    else
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1"
+            : "=v"(d) : "v"(x), "v"(y));
+    return d;
+}
+
 // ---------------------------------------------------------------- staging
 //
 // A staging job is 16 consecutive pixels of one image row.  Its raw bytes are
@@ -360,14 +386,13 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const int off0 = X0 - lo - xr0;        // LDS column of the first window column, 1..16
     const int rp = a.rp, depth = a.depth;
     const int vbw = vb_width(TW, win);
+    constexpr int VAP = TW + 32;                            // va_pitch
+    const int VBP = TW == 256 ? 256 + 32 : vbw + 32;       // vb_pitch (constant for 256 columns)
     uint8_t *ring = smem;
     uint16_t *Va1 = (uint16_t *)(smem + ring_bytes(TW, win));
-    uint16_t *Vb1 = Va1 + RB * TW;
-    uint32_t *Va2 = (uint32_t *)(Vb1 + RB * vbw);
-    uint32_t *Vb2 = Va2 + RB * TW;
-    // per-thread trash words, field-major ([4][kThreads] u32) so that the
-    // lanes of a wave write consecutive banks
-    uint32_t *trash = Vb2 + RB * vbw + tid;
+    uint16_t *Vb1 = Va1 + RB * VAP;
+    uint32_t *Va2 = (uint32_t *)(Vb1 + RB * VBP);
+    uint32_t *Vb2 = Va2 + RB * VAP;
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
     // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
@@ -389,22 +414,21 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const int c0 = 2 * tid;
     const bool vcol = c0 < rp;
     // Va index of column c: c - off0 - win + 1; Vb index: c - off0 + 1.
-    // Columns whose V is not needed in Va / Vb write to a trash slot instead,
-    // which keeps the vertical pass free of branches.
-    uint16_t *pa1[2], *pb1[2];
-    uint32_t *pa2[2], *pb2[2];
-    int sa[2], sb[2];
+    // Columns whose V is not needed in Va / Vb write to a trash entry of the
+    // same row instead, which keeps the vertical pass free of branches and
+    // every store at a fixed offset from its row.
+    int pa1[2], pa2[2], pb1[2], pb2[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int ia = c0 + h - off0 - win + 1, ib = c0 + h - off0 + 1;
-        const bool wa = vcol && ia >= 0 && ia < TW;
-        const bool wb = vcol && ib >= 0 && ib < vbw;
-        pa1[h] = wa ? Va1 + ia : (uint16_t *)(trash) + h;
-        pa2[h] = wa ? Va2 + v2_pos(ia, TW) : trash + kThreads;
-        pb1[h] = wb ? Vb1 + ib : (uint16_t *)(trash + 2 * kThreads) + h;
-        pb2[h] = wb ? Vb2 + v2_pos(ib, vbw) : trash + 3 * kThreads;
-        sa[h] = wa ? TW : 0;   // row strides (0 keeps trash in place)
-        sb[h] = wb ? vbw : 0;
+        const int c = c0 + h;
+        const int ia = c - off0 - win + 1, ib = c - off0 + 1;
+        const bool wa = ia >= 0 && ia < TW;
+        const bool wb = ib >= 0 && ib < vbw;
+        const int tr = c & 31;
+        pa1[h] = wa ? ia : TW + tr;
+        pa2[h] = wa ? v2_pos(ia, TW) : TW + tr;
+        pb1[h] = wb ? ib : vbw + tr;
+        pb2[h] = wb ? v2_pos(ib, vbw) : vbw + tr;
     }
     uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
     if (vcol) {
@@ -447,14 +471,15 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             for (int r = 0; r < RB; ++r) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int en = (int)((fn[r] >> (8 * h)) & 0xffu), lv = (int)((fo[r] >> (8 * h)) & 0xffu);
-                    const int d = en - lv;
+                    // d = f_in - f_out, V2 += d (f_in + f_out)
+                    const int d = h == 0 ? byte_sub<0>(fn[r], fo[r]) : byte_sub<1>(fn[r], fo[r]);
+                    const int e = h == 0 ? byte_add<0>(fn[r], fo[r]) : byte_add<1>(fn[r], fo[r]);
                     v1[h] += (uint32_t)d;
-                    v2[h] += (uint32_t)(d * (en + lv));
-                    pa1[h][r * sa[h]] = (uint16_t)v1[h];
-                    pa2[h][r * sa[h]] = v2[h];
-                    pb1[h][r * sb[h]] = (uint16_t)v1[h];
-                    pb2[h][r * sb[h]] = v2[h];
+                    v2[h] += (uint32_t)__mul24(d, e);
+                    Va1[r * VAP + pa1[h]] = (uint16_t)v1[h];
+                    Va2[r * VAP + pa2[h]] = v2[h];
+                    Vb1[r * VBP + pb1[h]] = (uint16_t)v1[h];
+                    Vb2[r * VBP + pb2[h]] = v2[h];
                 }
             }
         }
@@ -465,10 +490,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // store nothing) so the cross-lane scans see full 32-lane halves.
         const int y = y0 + hr;
         uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
-        load_u16<OPT>(Va1 + hr * TW + hs * OPT, A1);
-        load_u16<OPT>(Vb1 + hr * vbw + hs * OPT, B1);
-        load_v2<OPT>(Va2 + hr * TW, TW, hs, A2);
-        load_v2<OPT>(Vb2 + hr * vbw, vbw, hs, B2);
+        load_u16<OPT>(Va1 + hr * VAP + hs * OPT, A1);
+        load_u16<OPT>(Vb1 + hr * VBP + hs * OPT, B1);
+        load_v2<OPT>(Va2 + hr * VAP, TW, hs, A2);
+        load_v2<OPT>(Vb2 + hr * VBP, vbw, hs, B2);
         // starting value: window sum one column left of the tile (entries
         // 0 .. win-1 of the Vb row).  A uniform, not unrolled loop over
         // 32-entry blocks: reads stay below 32 * ceil(win / 32) <= vbw, and
@@ -478,7 +503,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 #pragma unroll 1
         for (int it = 0; it < nblk; ++it) {
             const int i = hs + it * TPR;
-            const uint32_t x1 = Vb1[hr * vbw + i], x2 = Vb2[hr * vbw + v2_pos(i, vbw)];
+            const uint32_t x1 = Vb1[hr * VBP + i], x2 = Vb2[hr * VBP + v2_pos(i, vbw)];
             h1 += i < win ? x1 : 0u;
             h2 += i < win ? x2 : 0u;
         }
