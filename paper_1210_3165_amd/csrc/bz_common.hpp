@@ -60,12 +60,15 @@ BZ_HD inline int ring_bytes(int tile_w, int win) {
 }
 // Width of the Vb rows: the tile, or the whole first window if that is wider.
 BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
-// Row pitches of the V arrays: the entries a row needs, then 32 trash entries
-// that take the writes of the columns the row does not need, so every column
-// writes at one fixed offset per row (lanes of a wave share a trash entry at
-// most in pairs).  For 256-column tiles vb_width is always 256.
-BZ_HD inline int va_pitch(int tile_w) { return tile_w + 32; }
-BZ_HD inline int vb_pitch(int tile_w, int win) { return vb_width(tile_w, win) + 32; }
+// Row pitches of the V arrays: the entries a row needs, then kTrash trash
+// entries that take the writes of the columns the row does not need, so every
+// column writes at one fixed offset per row (the few lanes that write trash
+// share an entry at most four to a wave).  16 keeps a 256-column win-15 tile
+// within 32 KiB of LDS, five workgroups per CU.  For 256-column tiles
+// vb_width is always 256.
+constexpr int kTrash = 16;
+BZ_HD inline int va_pitch(int tile_w) { return tile_w + kTrash; }
+BZ_HD inline int vb_pitch(int tile_w, int win) { return vb_width(tile_w, win) + kTrash; }
 // LDS layout: ring | Va1 [RB][va_pitch] u16 | Vb1 [RB][vb_pitch] u16 |
 // Va2 [RB][va_pitch] u32 | Vb2 [RB][vb_pitch] u32
 BZ_HD inline int tile_lds_bytes(int tile_w, int win) {

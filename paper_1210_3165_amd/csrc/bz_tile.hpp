@@ -386,8 +386,8 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const int off0 = X0 - lo - xr0;        // LDS column of the first window column, 1..16
     const int rp = a.rp, depth = a.depth;
     const int vbw = vb_width(TW, win);
-    constexpr int VAP = TW + 32;                            // va_pitch
-    const int VBP = TW == 256 ? 256 + 32 : vbw + 32;       // vb_pitch (constant for 256 columns)
+    constexpr int VAP = TW + kTrash;                        // va_pitch
+    const int VBP = TW == 256 ? 256 + kTrash : vbw + kTrash;  // vb_pitch (constant for 256 columns)
     uint8_t *ring = smem;
     uint16_t *Va1 = (uint16_t *)(smem + ring_bytes(TW, win));
     uint16_t *Vb1 = Va1 + RB * VAP;
@@ -399,15 +399,29 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // extra word a chunk may read past its last byte all lie inside the row.
     const bool clamp = !INT && (xr0 < 0 || xr0 + rp + 4 > a.W);
 
-    // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1
+    // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1.  Several
+    // blocks of RB rows are fetched before any of them is stored, so their
+    // loads are in flight together instead of one latency per block.
+    // The rows of the first step are requested together with the last blocks.
+    constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
+    Stager<C, INT> st[NS];
     Stager<C, INT> pre;  // rows of the next step, in flight while this one computes
     pre.init(a);
-    for (int r0 = 0; r0 < win; r0 += RB) {
-        const int nr = min(RB, win - r0);
-        pre.fetch(a, base + r0, nr, xr0, clamp);
-        pre.store(a, ring, r0, nr, xr0, clamp);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) st[u].init(a);
+    for (int r0 = 0; r0 < win; r0 += NS * RB) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int rr = r0 + u * RB;
+            if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
+        }
+        if (r0 + NS * RB >= win) pre.fetch(a, Y0 + hi, RB, xr0, clamp);
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int rr = r0 + u * RB;
+            if (rr < win) st[u].store(a, ring, rr, min(RB, win - rr), xr0, clamp);
+        }
     }
-    pre.fetch(a, Y0 + hi, RB, xr0, clamp);
     __syncthreads();
 
     // ---- vertical-pass ownership: LDS columns c0 = 2 tid and c0 + 1
@@ -424,7 +438,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const int ia = c - off0 - win + 1, ib = c - off0 + 1;
         const bool wa = ia >= 0 && ia < TW;
         const bool wb = ib >= 0 && ib < vbw;
-        const int tr = c & 31;
+        const int tr = c & (kTrash - 1);
         pa1[h] = wa ? ia : TW + tr;
         pa2[h] = wa ? v2_pos(ia, TW) : TW + tr;
         pb1[h] = wb ? ib : vbw + tr;
