@@ -224,11 +224,11 @@ __device__ __forceinline__ uint32_t scan32(uint32_t v) {
     return v;
 }
 
-// Total of the 32-lane half this lane belongs to, given its inclusive scan.
+// Total of the 32-lane half this lane belongs to, given its inclusive scan:
+// every lane reads the last lane of its half (ds_swizzle in bit mode with
+// or-mask 31, which works within 32-lane groups; no LDS memory is touched).
 __device__ __forceinline__ uint32_t half_total(uint32_t incl) {
-    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)incl, 31);
-    const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    return (threadIdx.x & 32) ? t1 : t0;
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)incl, 0x1f << 5);
 }
 
 // ---------------------------------------------------------------- decision
