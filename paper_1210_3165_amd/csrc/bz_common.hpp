@@ -46,10 +46,13 @@ struct PageArgs {
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Ring geometry.  rp covers the tile, its halo and up to 16 columns of
-// alignment slack.  depth holds every row one step touches (win + RB) and, when
-// the window reaches less than RB rows down, enough extra rows that the slots
-// refilled at the start of a step held no row the previous step still reads
-// as a window centre: depth >= hi + 2 RB.
+// alignment slack.  depth holds every row one step touches (win + RB).  The
+// next step's rows are written while this step's horizontal pass still reads
+// its window centres; they replace rows at least depth rows older, which must
+// be rows the vertical pass has finished with and not centres: with
+// depth = win + RB they are this step's leaving rows, and when the window
+// reaches less than RB rows down depth >= hi + 2 RB keeps them above the
+// centres.
 BZ_HD inline int ring_pitch(int tile_w, int win) { return round_up(tile_w + win + 15, 16); }
 BZ_HD inline int ring_depth(int win) {
     const int hi = win - 1 - win / 2;

@@ -462,13 +462,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const RowSauvola q_full = row_sauvola(a, n_full);
 
+    // The rows of the first step go in behind the start-up rows (slots the
+    // start-up reads do not touch); the rows of the second step are requested.
+    pre.store(a, ring, (Y0 + hi - base) % depth, RB, xr0, clamp);
+    if (Y0 + RB < Yend) pre.fetch(a, Y0 + RB + hi, RB, xr0, clamp);
+    __syncthreads();
+
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
-        // Rows of this step go into ring slots whose previous rows no thread
-        // reads any more (see ring_depth).
-        pre.store(a, ring, s_in, RB, xr0, clamp);
-        if (y0 + RB < Yend) pre.fetch(a, y0 + RB + hi, RB, xr0, clamp);
-        __syncthreads();
 
         // ---- vertical pass: two LDS columns per thread, RB rows, no branches
         if (vcol) {
@@ -582,6 +583,17 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
             }
         }
+        // The rows of the next step go into the slots of this step's leaving
+        // rows, which no thread reads after the vertical pass (see
+        // ring_depth); the centre rows read above are other slots.  Storing
+        // them here, before this step's output stores, means the wait for
+        // their loads (issued a step ago) does not also wait for output
+        // stores just issued: vector-memory waits count loads and stores
+        // together, in order.
+        if (y0 + RB < Yend) {
+            pre.store(a, ring, (y0 + RB + hi - base) % depth, RB, xr0, clamp);
+            if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
+        }
         if (y < Yend) {
             store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
             if (STATS) {
@@ -599,6 +611,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 }
             }
         }
+        __syncthreads();  // next step: ring rows stored, V rows free again
     }
 }
 
