@@ -40,6 +40,12 @@
  * Streams       `stream` is a hipStream_t passed as void*; NULL selects the
  *               default (null) stream.  Every call only enqueues work and
  *               returns; results are ready when the stream is synchronised.
+ * Graphs        binarize*, binarize_otsu, binarize_gs and
+ *               binarize_fmeasure_counts enqueue kernel launches only (no
+ *               memset, allocation or host synchronisation), so a caller
+ *               may capture them in a HIP graph and replay it.  The batch
+ *               object has its own graph mode and is not capturable: a run
+ *               waits on the host for its previous run.
  * Errors        0 on success, a negative BZ_ERR_* code otherwise.  Arguments
  *               are validated before anything is enqueued; on BZ_ERR_HIP the
  *               HIP error code is kept per thread (binarize_last_hip_error).
