@@ -115,7 +115,8 @@ void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int C, int win, fl
     a->n_tiles = p.tiles_x * p.tiles_y;
     a->rp = ring_pitch(p.tile_w, win);
     a->depth = ring_depth(win);
-    a->row_aligned = (((uintptr_t)img & 15) == 0 && ((int64_t)W * C) % 16 == 0) ? 1 : 0;
+    a->row_aligned =
+        (((uintptr_t)img & 15) == 0 && ((int64_t)W * C) % 16 == 0 && ((uintptr_t)out & 7) == 0) ? 1 : 0;
 }
 
 template <int TW, int C, int RULE, bool STATS>

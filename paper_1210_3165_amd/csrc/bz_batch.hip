@@ -205,7 +205,10 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, int *items, int *m
         a.n_tiles = a.tiles_x * ((p.H + th - 1) / th);
         a.rp = ring_pitch(tw, p.win);
         a.depth = ring_depth(p.win);
-        a.row_aligned = (((uintptr_t)p.img & 15) == 0 && ((int64_t)p.W_img * p.channels) % 16 == 0) ? 1 : 0;
+        a.row_aligned = (((uintptr_t)p.img & 15) == 0 && ((int64_t)p.W_img * p.channels) % 16 == 0 &&
+                         ((uintptr_t)p.out & 7) == 0)
+                            ? 1
+                            : 0;
         e.item0 = (int)per_kind[q];
         per_kind[q] += a.n_tiles;
         total += a.n_tiles;

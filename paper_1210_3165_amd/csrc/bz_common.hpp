@@ -40,7 +40,7 @@ struct PageArgs {
     int n_tiles;      // tiles_x * tiles_y
     int rp;           // LDS ring row pitch in bytes (multiple of 16)
     int depth;        // ring depth in rows
-    int row_aligned;  // img and the row pitch W*C are multiples of 16 bytes
+    int row_aligned;  // img and the row pitch W*C are multiples of 16 bytes, out of 8
 };
 
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }

@@ -464,23 +464,28 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     // The rows of the first step go in behind the start-up rows (slots the
     // start-up reads do not touch); the rows of the second step are requested.
-    pre.store(a, ring, (Y0 + hi - base) % depth, RB, xr0, clamp);
+    // Ring slots of the step's first entering row (image row y0 + hi), first
+    // leaving row (y0 - lo - 1) and first output row (y0), advanced by RB per
+    // step; slot 0 holds image row base = Y0 - lo - 1 and depth > win.
+    int s_in = win, s_out = 0, s_ctr = lo + 1;
+    const int ring_len = depth * rp;  // bytes of the ring
+    pre.store(a, ring, s_in, RB, xr0, clamp);
     if (Y0 + RB < Yend) pre.fetch(a, Y0 + RB + hi, RB, xr0, clamp);
     __syncthreads();
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
-        const int s_in = (y0 + hi - base) % depth;  // slot of the first entering row
-
         // ---- vertical pass: two LDS columns per thread, RB rows, no branches
         if (vcol) {
-            int se = s_in, sx = (y0 - Y0) % depth;  // entering / leaving row slots
+            int pe = s_in * rp, px = s_out * rp;  // byte offsets of the entering / leaving rows
             uint32_t fn[RB], fo[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                fn[r] = *(const uint16_t *)(ring + se * rp + c0);
-                fo[r] = *(const uint16_t *)(ring + sx * rp + c0);
-                se = (se + 1 == depth) ? 0 : se + 1;
-                sx = (sx + 1 == depth) ? 0 : sx + 1;
+                fn[r] = *(const uint16_t *)(ring + pe + c0);
+                fo[r] = *(const uint16_t *)(ring + px + c0);
+                pe += rp;
+                px += rp;
+                pe = pe == ring_len ? 0 : pe;
+                px = px == ring_len ? 0 : px;
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -538,7 +543,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const uint32_t b2 = half_total(h2i) + s2i - a2;
 
         // gray levels of the output row (centre of the window)
-        int sy = (y0 - base) % depth + hr;  // ring slot of this output row
+        int sy = s_ctr + hr;  // ring slot of this output row
         if (sy >= depth) sy -= depth;
         const int fo = sy * rp + off0 + lo + hs * OPT;
         const uint32_t fsh = (uint32_t)(fo & 3);
@@ -590,12 +595,22 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // their loads (issued a step ago) does not also wait for output
         // stores just issued: vector-memory waits count loads and stores
         // together, in order.
+        s_in = s_in + RB >= depth ? s_in + RB - depth : s_in + RB;
+        s_out = s_out + RB >= depth ? s_out + RB - depth : s_out + RB;
+        s_ctr = s_ctr + RB >= depth ? s_ctr + RB - depth : s_ctr + RB;
         if (y0 + RB < Yend) {
-            pre.store(a, ring, (y0 + RB + hi - base) % depth, RB, xr0, clamp);
+            pre.store(a, ring, s_in, RB, xr0, clamp);
             if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
         }
+        if (INT) {  // every row of the tile is inside the image; aligned output rows
+            uint8_t *p = a.out + (size_t)y * a.W + xs;
+            if (OPT == 8)
+                *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
+            else
+                *(uint32_t *)p = ow[0];
+        }
         if (y < Yend) {
-            store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
+            if (!INT) store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
             if (STATS) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
@@ -617,8 +632,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
 // Interior tiles take a specialised body: every staged row and column lies
 // inside the image and rows are 16-byte aligned, so staging needs no clamping
-// or masking and loads whole 16-byte chunks, and every window is whole
-// (n = win^2), so the Sauvola row constants are computed once per tile.  The
+// or masking and loads whole 16-byte chunks; every window is whole
+// (n = win^2), so the Sauvola row constants are computed once per tile; and
+// output rows are 8-byte aligned and wholly inside the image, so every thread
+// stores its outputs with one store.  The
 // choice is uniform per workgroup; both bodies produce identical bytes.
 template <int TW, int C, int RULE, bool STATS>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
