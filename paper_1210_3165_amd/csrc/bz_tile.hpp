@@ -356,17 +356,19 @@ __device__ __forceinline__ void load_u16(const uint16_t *p, uint32_t (&v)[OPT]) 
     }
 }
 
-// Entries OPT*h .. OPT*h+OPT-1 of a V2 row laid out by v2_pos.
+// Entries OPT*h .. OPT*h+OPT-1 of a V2 row laid out by v2_pos (second quads
+// of an 8-entry group hold their entries pairwise swapped).
 template <int OPT>
 __device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, uint32_t (&v)[OPT]) {
 #pragma unroll
     for (int i = 0; i < OPT / 4; ++i) {
         const int x = OPT * h + 4 * i;
-        const uint4 q = *(const uint4 *)(row + v2_pos(x, width));
-        v[4 * i] = q.x;
-        v[4 * i + 1] = q.y;
-        v[4 * i + 2] = q.z;
-        v[4 * i + 3] = q.w;
+        const uint4 q = *(const uint4 *)(row + v2_quad(x, width));
+        const bool sw = (x >> 2) & 1;  // OPT == 8: i == 1; OPT == 4: odd h
+        v[4 * i] = sw ? q.y : q.x;
+        v[4 * i + 1] = sw ? q.x : q.y;
+        v[4 * i + 2] = sw ? q.w : q.z;
+        v[4 * i + 3] = sw ? q.z : q.w;
     }
 }
 
@@ -545,12 +547,18 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // gray levels of the output row (centre of the window)
         int sy = s_ctr + hr;  // ring slot of this output row
         if (sy >= depth) sy -= depth;
+        // (X0 is a multiple of 16 and xr0 = X0 - ceil16(lo + 1), so the
+        // window centre of column X0 sits at LDS column off0 + lo =
+        // ceil16(lo + 1) and each thread's OPT bytes are OPT-aligned.)
         const int fo = sy * rp + off0 + lo + hs * OPT;
-        const uint32_t fsh = (uint32_t)(fo & 3);
-        const uint32_t *fq = (const uint32_t *)(smem + (fo & ~3));
         uint32_t fw[OPT / 4];
-#pragma unroll
-        for (int i = 0; i < OPT / 4; ++i) fw[i] = align_bytes(fq[i + 1], fq[i], fsh);
+        if (OPT == 8) {
+            const uint2 q = *(const uint2 *)(smem + fo);
+            fw[0] = q.x;
+            fw[OPT / 4 - 1] = q.y;
+        } else {
+            fw[0] = *(const uint32_t *)(smem + fo);
+        }
 
         const int ny = INT ? win : min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
         const int xs = X0 + hs * OPT;
