@@ -511,23 +511,27 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // Every group runs (rows past the tile compute on stale LDS data and
         // store nothing) so the cross-lane scans see full 32-lane halves.
         const int y = y0 + hr;
+        // starting value: window sum one column left of the tile (entries
+        // 0 .. win-1 of the Vb row), summed over 32-entry blocks: reads stay
+        // below 32 * ceil(win / 32) <= vbw, and entries at i >= win are
+        // masked after the read.  The first block is read before the tile's
+        // own V entries, so the wait for it is not a wait for them; further
+        // blocks (win > 32) follow in a uniform loop that is not unrolled.
+        const uint32_t x1 = Vb1[hr * VBP + hs], x2 = Vb2[hr * VBP + v2_pos(hs, vbw)];
         uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
         load_u16<OPT>(Va1 + hr * VAP + hs * OPT, A1);
         load_u16<OPT>(Vb1 + hr * VBP + hs * OPT, B1);
         load_v2<OPT>(Va2 + hr * VAP, TW, hs, A2);
         load_v2<OPT>(Vb2 + hr * VBP, vbw, hs, B2);
-        // starting value: window sum one column left of the tile (entries
-        // 0 .. win-1 of the Vb row).  A uniform, not unrolled loop over
-        // 32-entry blocks: reads stay below 32 * ceil(win / 32) <= vbw, and
-        // entries at i >= win are masked after the read.
-        uint32_t h1 = 0, h2 = 0;
+        __builtin_amdgcn_sched_barrier(0);  // keep every read above issued before any wait
+        uint32_t h1 = hs < win ? x1 : 0u, h2 = hs < win ? x2 : 0u;
         const int nblk = (win + TPR - 1) / TPR;
 #pragma unroll 1
-        for (int it = 0; it < nblk; ++it) {
+        for (int it = 1; it < nblk; ++it) {
             const int i = hs + it * TPR;
-            const uint32_t x1 = Vb1[hr * VBP + i], x2 = Vb2[hr * VBP + v2_pos(i, vbw)];
-            h1 += i < win ? x1 : 0u;
-            h2 += i < win ? x2 : 0u;
+            const uint32_t z1 = Vb1[hr * VBP + i], z2 = Vb2[hr * VBP + v2_pos(i, vbw)];
+            h1 += i < win ? z1 : 0u;
+            h2 += i < win ? z2 : 0u;
         }
         // running sums of the entering-minus-leaving columns
         uint32_t E1[OPT], E2[OPT];
