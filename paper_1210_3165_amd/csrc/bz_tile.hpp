@@ -164,9 +164,9 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
 // The job of this thread for a block of up to RB rows: row i = job / nq of
 // the block, chunk q = job % nq (nq = rp / 16 chunks per row).  RB * rp / 16
 // <= 256 gives at most one job per thread.  Rows outside the image load a clamped
-// row (always a valid address) and store zeros.  INT: an interior tile (every
-// staged row and column lies inside the image, rows 16-byte aligned), which
-// needs no clamping, no masking and loads whole 16-byte chunks.
+// row (always a valid address) and store zeros.  INT: a tile whose staged
+// columns all lie inside the image on 16-byte-aligned rows, which needs no
+// column clamping or masking and loads whole 16-byte chunks.
 template <int C, bool INT>
 struct Stager {
     RawChunk<C> k;
@@ -183,13 +183,9 @@ struct Stager {
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
         if (job_row < nrows) {
             const int row = row0 + job_row;
-            if (INT) {
-                fetch_chunk<C, true>(k, a.img + (size_t)row * (size_t)a.W * C, xr0 + 16 * job_q, a.W, false);
-            } else {
-                in_image = row >= 0 && row < a.H;
-                const int rc = min(max(row, 0), a.H - 1);
-                fetch_chunk<C, false>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
-            }
+            in_image = row >= 0 && row < a.H;
+            const int rc = min(max(row, 0), a.H - 1);
+            fetch_chunk<C, INT>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
         }
     }
 
@@ -199,7 +195,7 @@ struct Stager {
         int sl = slot0 + job_row;
         if (sl >= a.depth) sl -= a.depth;
         uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
-        if (!INT && !in_image) v = make_uint4(0u, 0u, 0u, 0u);
+        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
         *(uint4 *)(ring + sl * a.rp + 16 * job_q) = v;
     }
 };
@@ -331,10 +327,21 @@ __device__ __forceinline__ int floor16(int x) { return x & ~15; }  // two's comp
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
 // contiguous run of tiles so neighbouring tiles (which share halo columns and
-// rows) meet in the same L2.
+// rows) meet in the same L2.  Inside a run of L tiles, workgroup i takes tile
+// (i % G) * R + i / G (G groups of R = ceil(L / G) tiles, the last groups one
+// tile shorter): a bijection of the run.  Workgroups placed on the same CU
+// (i a multiple of the XCD's CU count apart) then take tiles G apart within a
+// group instead of tiles a CU count apart, which on power-of-two page widths
+// stacks them in one tile column; the slower edge-column tiles are thereby
+// spread over the CUs instead of loading a few of them four times.
+template <int G = 8>
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
+    const int L = q + (x < r ? 1 : 0);
+    const int R = (L + G - 1) / G, full = L - (R - 1) * G;  // groups with R tiles
+    const int g = i % G, k = i / G;
+    const int j = g < full ? g * R + k : full * R + (g - full) * (R - 1) + k;
+    return x * q + (x < r ? x : r) + j;
 }
 
 template <int OPT>
@@ -564,16 +571,20 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             fw[0] = *(const uint32_t *)(smem + fo);
         }
 
-        const int ny = INT ? win : min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
+        // every window of the step's rows has win rows (uniform per step)
+        const bool full_rows = y0 - lo >= 0 && y0 + RB - 1 + hi <= a.H - 1;
+        const int ny = min(y + hi, a.H - 1) - max(y - lo, 0) + 1;
         const int xs = X0 + hs * OPT;
         uint32_t ow[OPT / 4];
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float sqv[OPT];
         if (x_inside) {  // n = win * ny for the whole row segment
-            const uint32_t n = INT ? n_full : (uint32_t)__mul24(win, ny);
+            const bool full = INT && full_rows;
+            const uint32_t n = full ? n_full : (uint32_t)__mul24(win, ny);
             if (RULE == 0) {
-                const RowSauvola q = INT ? q_full : row_sauvola(a, n);
+                RowSauvola q = q_full;
+                if (!full) q = row_sauvola(a, n);
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
                     const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
@@ -614,15 +625,16 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             pre.store(a, ring, s_in, RB, xr0, clamp);
             if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
         }
-        if (INT) {  // every row of the tile is inside the image; aligned output rows
-            uint8_t *p = a.out + (size_t)y * a.W + xs;
-            if (OPT == 8)
-                *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
-            else
-                *(uint32_t *)p = ow[0];
-        }
         if (y < Yend) {
-            if (!INT) store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
+            if (INT) {  // the thread's outputs lie inside the row, and rows are 8-byte aligned
+                uint8_t *p = a.out + (size_t)y * a.W + xs;
+                if (OPT == 8)
+                    *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
+                else
+                    *(uint32_t *)p = ow[0];
+            } else {
+                store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
+            }
             if (STATS) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
@@ -642,21 +654,20 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 }
 
-// Interior tiles take a specialised body: every staged row and column lies
-// inside the image and rows are 16-byte aligned, so staging needs no clamping
-// or masking and loads whole 16-byte chunks; every window is whole
-// (n = win^2), so the Sauvola row constants are computed once per tile; and
-// output rows are 8-byte aligned and wholly inside the image, so every thread
+// Interior tiles take a specialised body: every staged column lies inside the
+// image and rows are 16-byte aligned, so staging needs no column clamping or
+// masking and loads whole 16-byte chunks; every window spans win columns, so
+// steps whose windows also span win rows (all but the first and last steps of
+// the top and bottom tiles) use n = win^2 and the Sauvola row constants
+// computed once per tile; and output rows are 8-byte aligned, so every thread
 // stores its outputs with one store.  The
 // choice is uniform per workgroup; both bodies produce identical bytes.
 template <int TW, int C, int RULE, bool STATS>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int X0 = tx * TW, Y0 = ty * a.tile_h;
+    const int X0 = (tile % a.tiles_x) * TW;
     const int xr0 = floor16(X0 - a.lo - 1);
     const bool interior = a.row_aligned && xr0 >= 0 && xr0 + a.rp + 4 <= a.W && X0 - a.lo >= 0 &&
-                          X0 + TW - 1 + a.hi <= a.W - 1 && Y0 - a.lo - 1 >= 0 &&
-                          Y0 + a.tile_h - 1 + a.hi <= a.H - 1;
+                          X0 + TW - 1 + a.hi <= a.W - 1;
     if (interior)
         process_tile<TW, C, RULE, STATS, true>(a, tile, smem);
     else
