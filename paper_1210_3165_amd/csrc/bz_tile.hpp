@@ -233,9 +233,10 @@ __device__ __forceinline__ uint32_t half_total(uint32_t incl) {
 // m = S1 / n and s = sqrt(D) / n where D = n S2 - S1^2 is formed exactly in
 // fp64 (every term is an integer below 2^53).
 //
-//   Sauvola (Eq. 4), interior rows (n fixed for the row):
+//   Sauvola (Eq. 4), steps whose windows are all whole (n = win^2 for the
+//   whole tile, so c1/n and c2/n^2 are computed once per tile):
 //       f < t  <=>  f < S1 (c1/n + (c2/n^2) sqrt(D)),  c1 = 1 - k, c2 = k / R
-//   Sauvola, general n:
+//   Sauvola, clipped windows (n per pixel, no division):
 //       f < t  <=>  (n f) n < S1 (n c1 + c2 sqrt(D))
 //   Niblack:
 //       f < m + k s  <=>  n f - S1 < k sqrt(D)          (n f, S1 exact integers)
@@ -244,7 +245,7 @@ __device__ __forceinline__ uint32_t half_total(uint32_t incl) {
 // (D = 0) gives f = t and the output 255.  A Sauvola call with k = 0 is the
 // same rule (t = m) and is routed to the Niblack form by the host.
 
-// Per-row constants of the interior Sauvola form.
+// Per-tile constants of the whole-window Sauvola form.
 struct RowSauvola {
     double nd;
     float c1n, c2n2;
@@ -467,7 +468,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     const int hr = tid / TPR, hs = tid % TPR;
     const bool x_inside = INT || (X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1);
-    // interior tiles: every window is whole, n = win^2 on every row
+    // steps whose windows are all whole: n = win^2, Sauvola constants per tile
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const RowSauvola q_full = row_sauvola(a, n_full);
 
@@ -579,32 +580,25 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float sqv[OPT];
-        if (x_inside) {  // n = win * ny for the whole row segment
-            const bool full = INT && full_rows;
-            const uint32_t n = full ? n_full : (uint32_t)__mul24(win, ny);
+        if (x_inside && full_rows) {  // uniform: every window of the step is win x win
             if (RULE == 0) {
-                RowSauvola q = q_full;
-                if (!full) q = row_sauvola(a, n);
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q, sqv[j]);
+                    const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q_full, sqv[j]);
                     ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
                 }
             } else {
-                const double nd = (double)n;
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const uint32_t S1 = b1 + E1[j];
-                    sqv[j] = exact_sqrt_d(nd, S1, b2 + E2[j]);
-                    const bool dark = (float)((int)__umul24(n, byte_at(fw, j)) - (int)S1) < a.k * sqv[j];
+                    const bool dark = dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n_full, sqv[j]);
                     ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
                 }
             }
-        } else {
+        } else {  // clipped windows: n per pixel, no division
 #pragma unroll
             for (int j = 0; j < OPT; ++j) {
                 const int X = xs + j;
-                const int nx = min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
+                const int nx = x_inside ? win : min(X + hi, a.W - 1) - max(X - lo, 0) + 1;
                 const uint32_t n = (uint32_t)__mul24(nx, ny);
                 const bool dark = RULE == 0 ? dark_sauvola(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j])
                                             : dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j]);
@@ -656,11 +650,11 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
 // Interior tiles take a specialised body: every staged column lies inside the
 // image and rows are 16-byte aligned, so staging needs no column clamping or
-// masking and loads whole 16-byte chunks; every window spans win columns, so
-// steps whose windows also span win rows (all but the first and last steps of
-// the top and bottom tiles) use n = win^2 and the Sauvola row constants
-// computed once per tile; and output rows are 8-byte aligned, so every thread
-// stores its outputs with one store.  The
+// masking and loads whole 16-byte chunks, and output rows are 8-byte aligned,
+// so every thread stores its outputs with one store.  (Every tile whose
+// windows all span win columns, interior or not, decides steps whose windows
+// also span win rows with the per-tile constants, and the first and last steps
+// of the top and bottom tiles with per-pixel n.)  The
 // choice is uniform per workgroup; both bodies produce identical bytes.
 template <int TW, int C, int RULE, bool STATS>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
