@@ -164,9 +164,10 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
 // The job of this thread for a block of up to RB rows: row i = job / nq of
 // the block, chunk q = job % nq (nq = rp / 16 chunks per row).  RB * rp / 16
 // <= 256 gives at most one job per thread.  Rows outside the image load a clamped
-// row (always a valid address) and store zeros.  INT: a tile whose staged
-// columns all lie inside the image on 16-byte-aligned rows, which needs no
-// column clamping or masking and loads whole 16-byte chunks.
+// row (always a valid address) and store zeros.  INT: a page whose rows are
+// 16-byte aligned and a multiple of 16 pixels wide, so every chunk lies wholly
+// inside or wholly outside the image: chunks are loaded whole with one 16-byte
+// load, and chunks outside load a clamped chunk and store zeros.
 template <int C, bool INT>
 struct Stager {
     RawChunk<C> k;
@@ -183,9 +184,14 @@ struct Stager {
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
         if (job_row < nrows) {
             const int row = row0 + job_row;
+            int xs = xr0 + 16 * job_q;
             in_image = row >= 0 && row < a.H;
+            if (INT) {
+                in_image = in_image && xs >= 0 && xs < a.W;
+                xs = min(max(xs, 0), a.W - 16);
+            }
             const int rc = min(max(row, 0), a.H - 1);
-            fetch_chunk<C, INT>(k, a.img + (size_t)rc * (size_t)a.W * C, xr0 + 16 * job_q, a.W, clamp);
+            fetch_chunk<C, INT>(k, a.img + (size_t)rc * (size_t)a.W * C, xs, a.W, clamp);
         }
     }
 
@@ -467,7 +473,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
-    const bool x_inside = INT || (X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1);
+    const bool x_inside = X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1;
     // steps whose windows are all whole: n = win^2, Sauvola constants per tile
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const RowSauvola q_full = row_sauvola(a, n_full);
@@ -620,12 +626,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
         }
         if (y < Yend) {
-            if (INT) {  // the thread's outputs lie inside the row, and rows are 8-byte aligned
-                uint8_t *p = a.out + (size_t)y * a.W + xs;
-                if (OPT == 8)
-                    *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
-                else
-                    *(uint32_t *)p = ow[0];
+            if (INT) {  // W is a multiple of 16: the thread's outputs lie wholly inside or outside
+                if (xs < a.W) {
+                    uint8_t *p = a.out + (size_t)y * a.W + xs;
+                    if (OPT == 8)
+                        *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
+                    else
+                        *(uint32_t *)p = ow[0];
+                }
             } else {
                 store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
             }
@@ -648,21 +656,17 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 }
 
-// Interior tiles take a specialised body: every staged column lies inside the
-// image and rows are 16-byte aligned, so staging needs no column clamping or
-// masking and loads whole 16-byte chunks, and output rows are 8-byte aligned,
-// so every thread stores its outputs with one store.  (Every tile whose
-// windows all span win columns, interior or not, decides steps whose windows
-// also span win rows with the per-tile constants, and the first and last steps
-// of the top and bottom tiles with per-pixel n.)  The
-// choice is uniform per workgroup; both bodies produce identical bytes.
+// Pages with aligned rows take a specialised body (a uniform choice per
+// launch): input rows 16-byte aligned and a multiple of 16 pixels wide, so
+// every 16-pixel chunk lies wholly inside or outside the image and staging
+// loads whole chunks with no per-byte masking; output rows 8-byte aligned, so
+// every thread stores its outputs with one store.  Both bodies produce
+// identical bytes.  In either, tiles whose windows all span win columns decide
+// steps whose windows also span win rows with the per-tile constants, and
+// every other step with per-pixel n.
 template <int TW, int C, int RULE, bool STATS>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
-    const int X0 = (tile % a.tiles_x) * TW;
-    const int xr0 = floor16(X0 - a.lo - 1);
-    const bool interior = a.row_aligned && xr0 >= 0 && xr0 + a.rp + 4 <= a.W && X0 - a.lo >= 0 &&
-                          X0 + TW - 1 + a.hi <= a.W - 1;
-    if (interior)
+    if (a.row_aligned)
         process_tile<TW, C, RULE, STATS, true>(a, tile, smem);
     else
         process_tile<TW, C, RULE, STATS, false>(a, tile, smem);
