@@ -235,6 +235,29 @@ def test_interior_tiles_full_compare(bz, oracle_mod, C, rule, win, k):
     assert np.array_equal(out.cpu().numpy(), aligned)
 
 
+@pytest.mark.parametrize("H,W,win", [(33, 16, 15), (40, 16, 101), (70, 48, 61), (129, 272, 31),
+                                     (40, 272, 255), (60, 528, 101), (64, 1040, 15)])
+def test_aligned_pages_outside_chunks(bz, oracle_mod, H, W, win):
+    """Pages whose rows are 16-byte aligned take the aligned-staging body on
+    every tile, including tiles whose staged columns reach whole 16-pixel
+    chunks past the left or right edge (staged as zeros) and pages narrower
+    than one tile: compared with the oracle pixel by pixel, and with the same
+    page one byte off alignment (general body), byte for byte."""
+    import pagegen
+    assert W % 16 == 0 and oracle_cost(H, W, win) < 6e8
+    for C in (1, 3):
+        img = pagegen.page(H, W, max(1, pagegen.strokes_for(H, W)), seed=H + W + win + C, channels=C)
+        for rule, k in ((0, 0.5), (1, -0.2)):
+            full_check(bz, oracle_mod, img, win, k, 128.0, rule, f"aligned {H}x{W}x{C} win {win}")
+            aligned = gpu_out(bz, img, win, f32(k), 128.0, rule)
+            buf = torch.zeros(img.size + 16, dtype=torch.uint8, device="cuda")
+            shifted = buf[1:1 + img.size].view(*img.shape)
+            shifted.copy_(torch.from_numpy(img))
+            out = bz.binarize(shifted, win, f32(k), 128.0, rule)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), aligned), (H, W, C, win, rule)
+
+
 # ------------------------------------------------------------ full size, sampled
 
 def sample_points(H, W, win, n, seed):
