@@ -82,14 +82,19 @@ BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
 // Position of entry x in a V2 row of `width` entries.  Thread h of a row group
 // reads entries 8h .. 8h+7 as two 16-byte quads; quads 8h..8h+3 of all threads
 // are packed first and quads 8h+4..8h+7 after width/2, so each 128-bit read of
-// a wave covers consecutive addresses.  Inside the second quad neighbouring
-// entries trade places (8h+4..8h+7 stored as 5 4 7 6).  The vertical pass
-// writes every other entry in one instruction; without the swap the entries of
-// both quads would fall on even banks only (quads start on multiples of four
-// words), two lanes to a bank, and with it the second quad's entries take the
-// odd banks.
+// a wave covers consecutive addresses.  With SW (256-column tiles), inside the
+// second quad neighbouring entries trade places (8h+4..8h+7 stored as
+// 5 4 7 6).  The vertical pass writes every other entry in one instruction;
+// without the swap the entries of both quads would fall on even banks only
+// (quads start on multiples of four words), two lanes to a bank, and with it
+// the second quad's entries take the odd banks.  128-column tiles, whose
+// threads read one quad each, keep the plain order: there the swap would cost
+// a per-lane select on every read.
 BZ_HD inline int v2_quad(int x, int width) { return ((x >> 3) << 2) + (((x >> 2) & 1) ? width / 2 : 0); }
-BZ_HD inline int v2_pos(int x, int width) { return v2_quad(x, width) + ((x & 3) ^ ((x >> 2) & 1)); }
+template <bool SW>
+BZ_HD inline int v2_pos(int x, int width) {
+    return v2_quad(x, width) + (SW ? ((x & 3) ^ ((x >> 2) & 1)) : (x & 3));
+}
 
 // HIP error of the last failed runtime call on this thread (kept by the
 // single-page entry points and the batch entry points alike).

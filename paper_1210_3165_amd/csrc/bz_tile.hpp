@@ -370,15 +370,15 @@ __device__ __forceinline__ void load_u16(const uint16_t *p, uint32_t (&v)[OPT]) 
     }
 }
 
-// Entries OPT*h .. OPT*h+OPT-1 of a V2 row laid out by v2_pos (second quads
-// of an 8-entry group hold their entries pairwise swapped).
+// Entries OPT*h .. OPT*h+OPT-1 of a V2 row laid out by v2_pos<OPT == 8>
+// (with OPT == 8 the second quad holds its entries pairwise swapped).
 template <int OPT>
 __device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, uint32_t (&v)[OPT]) {
 #pragma unroll
     for (int i = 0; i < OPT / 4; ++i) {
         const int x = OPT * h + 4 * i;
         const uint4 q = *(const uint4 *)(row + v2_quad(x, width));
-        const bool sw = (x >> 2) & 1;  // OPT == 8: i == 1; OPT == 4: odd h
+        const bool sw = OPT == 8 && i == 1;
         v[4 * i] = sw ? q.y : q.x;
         v[4 * i + 1] = sw ? q.x : q.y;
         v[4 * i + 2] = sw ? q.w : q.z;
@@ -456,9 +456,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const bool wb = ib >= 0 && ib < vbw;
         const int tr = c & (kTrash - 1);
         pa1[h] = wa ? ia : TW + tr;
-        pa2[h] = wa ? v2_pos(ia, TW) : TW + tr;
+        pa2[h] = wa ? v2_pos<OPT == 8>(ia, TW) : TW + tr;
         pb1[h] = wb ? ib : vbw + tr;
-        pb2[h] = wb ? v2_pos(ib, vbw) : vbw + tr;
+        pb2[h] = wb ? v2_pos<OPT == 8>(ib, vbw) : vbw + tr;
     }
     uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
     if (vcol) {
@@ -525,25 +525,21 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // Every group runs (rows past the tile compute on stale LDS data and
         // store nothing) so the cross-lane scans see full 32-lane halves.
         const int y = y0 + hr;
-        // starting value: window sum one column left of the tile (entries
-        // 0 .. win-1 of the Vb row), summed over 32-entry blocks: reads stay
-        // below 32 * ceil(win / 32) <= vbw, and entries at i >= win are
-        // masked after the read.  The first block is read before the tile's
-        // own V entries, so the wait for it is not a wait for them; further
-        // blocks (win > 32) follow in a uniform loop that is not unrolled.
-        const uint32_t x1 = Vb1[hr * VBP + hs], x2 = Vb2[hr * VBP + v2_pos(hs, vbw)];
         uint32_t A1[OPT], B1[OPT], A2[OPT], B2[OPT];
         load_u16<OPT>(Va1 + hr * VAP + hs * OPT, A1);
         load_u16<OPT>(Vb1 + hr * VBP + hs * OPT, B1);
         load_v2<OPT>(Va2 + hr * VAP, TW, hs, A2);
         load_v2<OPT>(Vb2 + hr * VBP, vbw, hs, B2);
-        __builtin_amdgcn_sched_barrier(0);  // keep every read above issued before any wait
-        uint32_t h1 = hs < win ? x1 : 0u, h2 = hs < win ? x2 : 0u;
+        // starting value: window sum one column left of the tile (entries
+        // 0 .. win-1 of the Vb row).  A uniform, not unrolled loop over
+        // 32-entry blocks: reads stay below 32 * ceil(win / 32) <= vbw, and
+        // entries at i >= win are masked after the read.
+        uint32_t h1 = 0, h2 = 0;
         const int nblk = (win + TPR - 1) / TPR;
 #pragma unroll 1
-        for (int it = 1; it < nblk; ++it) {
+        for (int it = 0; it < nblk; ++it) {
             const int i = hs + it * TPR;
-            const uint32_t z1 = Vb1[hr * VBP + i], z2 = Vb2[hr * VBP + v2_pos(i, vbw)];
+            const uint32_t z1 = Vb1[hr * VBP + i], z2 = Vb2[hr * VBP + v2_pos<OPT == 8>(i, vbw)];
             h1 += i < win ? z1 : 0u;
             h2 += i < win ? z2 : 0u;
         }
