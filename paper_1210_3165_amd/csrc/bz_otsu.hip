@@ -2,7 +2,8 @@
 // baseline (Sec. 1, Eq. 2) with its threshold T from Otsu's method.
 //
 //   otsu_hist    one workgroup per CU streams its share of the image once (16
-//                pixels per lane per step, 16-byte loads), reduces every pixel
+//                pixels per lane per load, 16-byte loads, up to 4 loads in
+//                flight per lane), reduces every pixel
 //                to its Eq. 1 gray level and counts it in LDS with one
 //                sub-histogram per lane position, laid out [level][lane]: the
 //                64 lanes of a wave always hit 64 different banks, whatever
@@ -184,19 +185,22 @@ __global__ __launch_bounds__(kHistThreads) void otsu_hist(const uint8_t *__restr
 
     const long stride = (long)gridDim.x * kHistThreads;
     if (ALIGNED) {
+        // rounds of U chunks per thread, all U loads issued before any is
+        // counted: a page of a few Mpx is one or two rounds, so the wait is
+        // one memory latency per round instead of one per chunk
+        constexpr int U = C == 1 ? 4 : 2;
         const long nchunks = npx / kPx;
-        long j = (long)blockIdx.x * kHistThreads + tid;
-        uint32_t cur[4 * C];
-        if (j < nchunks) load_chunk<C>(img + j * (kPx * C), cur);
-        while (j < nchunks) {
-            const long jn = j + stride;
-            uint32_t nxt[4 * C];
-            if (jn < nchunks) load_chunk<C>(img + jn * (kPx * C), nxt);
+        for (long j0 = (long)blockIdx.x * kHistThreads + tid; j0 < nchunks; j0 += U * stride) {
+            uint32_t w[U][4 * C];
 #pragma unroll
-            for (int p = 0; p < kPx; ++p) BZ_COUNT(level<C>(cur, p));
+            for (int u = 0; u < U; ++u)
+                if (j0 + u * stride < nchunks) load_chunk<C>(img + (j0 + u * stride) * (kPx * C), w[u]);
 #pragma unroll
-            for (int i = 0; i < 4 * C; ++i) cur[i] = nxt[i];
-            j = jn;
+            for (int u = 0; u < U; ++u)
+                if (j0 + u * stride < nchunks) {
+#pragma unroll
+                    for (int p = 0; p < kPx; ++p) BZ_COUNT(level<C>(w[u], p));
+                }
         }
         // the last npx % 16 pixels
         if (blockIdx.x == 0)
