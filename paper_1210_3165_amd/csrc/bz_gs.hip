@@ -13,11 +13,23 @@
 //
 // One workgroup makes a tile of 128 x 32 outputs.  It stages the gray levels
 // of the tile and its r-wide halo into LDS (Eq. 1 applied on the way; pixels
-// outside the image stage as 0 and are left out of n'), then every lane walks
-// the structure's lines through its output pixel: S1' and S2' are exact 32-bit
-// sums (S2' < 2^27), n' has a closed form per line.  The decision reuses the
-// exact-sum helpers of the full-window kernel (D' = n' S2' - S1'^2 formed
-// exactly, scaled fp32 comparison), so the same error bound holds.
+// outside the image stage as 0 and are left out of n').  The line sums are
+// then sliding sums, O(1) per pixel and line instead of the 2r + 1 samples of
+// a direct walk:
+//   rows       128 walkers (32 rows x 4 segments of 32 outputs) slide along
+//              the rows,
+//   diagonals  159 walkers, one per diagonal crossing the tile, slide down
+//              and right from the tile's top or left edge,
+//   anti-diagonals  159 walkers slide down and left from the top or right
+//              edge,
+// each pass adding its line sums of f and f^2 into an LDS accumulator per
+// output (a barrier between passes), and finally 256 walkers, two per column,
+// slide down the columns, add the column line, remove the extra copies of the
+// centre and decide.  Each walker pays 2r + 1 samples once to start.  S1' and
+// S2' are exact 32-bit sums (S2' < 2^27); n' has a closed form per line.  The
+// decision reuses the exact-sum helpers of the full-window kernel
+// (D' = n' S2' - S1'^2 formed exactly, scaled fp32 comparison), so the same
+// error bound holds.
 //
 // F-measure.  Counts TP (out == 0 where the ground truth marks text), FP
 // (out == 0 on background) and FN (out != 0 on text) in 64-bit counters.
@@ -50,8 +62,13 @@ struct GsArgs {
     PageArgs dec; // k, c1 = 1 - k, c2 = k / R' for the decision helpers
 };
 
-__host__ __device__ inline int gs_pitch(int r) { return round_up(kGsTW + 2 * r, 4); }
-__host__ __device__ inline int gs_lds(int r) { return (kGsTH + 2 * r) * gs_pitch(r); }
+// Staged row pitch: at least the tile plus halo, and an odd number of words,
+// so that walkers on consecutive rows read different banks.
+__host__ __device__ inline int gs_pitch(int r) { return round_up(kGsTW + 2 * r, 8) + 4; }
+// Accumulator row pitch in words (odd for the same reason).
+constexpr int kGsAccPitch = kGsTW + 1;
+__host__ __device__ inline int gs_stage_bytes(int r) { return round_up((kGsTH + 2 * r) * gs_pitch(r), 16); }
+__host__ __device__ inline int gs_lds(int r) { return gs_stage_bytes(r) + 2 * 4 * kGsTH * kGsAccPitch; }
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
@@ -65,58 +82,162 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
     const int x0 = tx * kGsTW, y0 = ty * kGsTH;
     const int r = g.r, rows = kGsTH + 2 * r, cols = kGsTW + 2 * r;
 
-    // stage the tile and its halo as gray levels (0 outside the image)
-    for (int ry = 0; ry < rows; ++ry) {
-        const int yy = y0 - r + ry;
-        const bool row_in = yy >= 0 && yy < g.H;
-        const uint8_t *src = g.img + (size_t)(row_in ? yy : 0) * g.W * C;
-        for (int rx = tid; rx < cols; rx += kGsThreads) {
-            const int xx = x0 - r + rx;
-            uint32_t v = 0;
-            if (row_in && xx >= 0 && xx < g.W) {
-                if (C == 1)
-                    v = src[xx];
-                else
-                    v = gray_of(src[3 * xx], src[3 * xx + 1], src[3 * xx + 2]);
+    // stage the tile and its halo as gray levels (0 outside the image): the
+    // rows x cols pixels in row-major order, pixel i = tid + 256 j; each lane
+    // issues the loads of 8 pixels before storing any, so the staging waits
+    // for memory once per 2048 pixels instead of once per row (larger batches
+    // measured slower: the per-pixel address and bounds work dominates)
+    {
+        constexpr int kB = 8;
+        const int total = rows * cols;
+        const int dq = kGsThreads / cols, dr = kGsThreads - dq * cols;  // (row, col) step of 256 pixels
+        int ry = tid / cols, rx = tid - (tid / cols) * cols;
+        for (int i0 = tid; i0 < total; i0 += kB * kGsThreads) {
+            uint32_t v[kB];
+            int so[kB];  // LDS offset of pixel u
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                so[u] = ry * g.pitch + rx;
+                v[u] = 0u;
+                const int yy = y0 - r + ry, xx = x0 - r + rx;
+                if (i0 + u * kGsThreads < total && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) {
+                    const uint8_t *q = g.img + ((size_t)yy * g.W + xx) * C;
+                    v[u] = C == 1 ? (uint32_t)q[0] : gray_of(q[0], q[1], q[2]);
+                }
+                rx += dr;
+                ry += dq;
+                if (rx >= cols) {
+                    rx -= cols;
+                    ++ry;
+                }
             }
-            lds[ry * g.pitch + rx] = (uint8_t)v;
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+                if (i0 + u * kGsThreads < total) lds[so[u]] = (uint8_t)v[u];
         }
     }
     __syncthreads();
 
+    const int P = g.pitch, w2 = 2 * r;
+    uint32_t *acc1 = reinterpret_cast<uint32_t *>(lds + gs_stage_bytes(r));  // [kGsTH][kGsAccPitch]
+    uint32_t *acc2 = acc1 + kGsTH * kGsAccPitch;
+    constexpr bool HV = ST != BZ_GS_X;    // the row and the column through the centre
+    constexpr bool DG = ST != BZ_GS_PLUS;  // the two diagonals
+    // Staged coordinates: output (cx, cy) sits at row cy + r, column cx + r.
+
+    // A walker starts with the line sum of its first cell (2r + 1 samples) and
+    // slides: cell k adds the sample entering at staged offset in0 + k * din
+    // and drops the one leaving at out0 + (k - 1) * dout, for L cells whose
+    // accumulators sit at acc0 + k * dacc.  Reads are issued four cells at a
+    // time, so each LDS round trip serves four cells.
+    auto walk = [&](int first, int step_first, int in0, int din, int out0, int dout, int acc0, int dacc, int L,
+                    bool add) {
+        uint32_t a = 0, b = 0;
+        for (int t = 0; t <= w2; ++t) {
+            const uint32_t v = lds[first + t * step_first];
+            a += v;
+            b += __umul24(v, v);
+        }
+        for (int k0 = 0; k0 < L; k0 += 4) {
+            uint32_t vi[4], vo[4], c1[4], c2[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + s;
+                vi[s] = vo[s] = c1[s] = c2[s] = 0u;
+                if (k < L) {
+                    if (k > 0) {
+                        vi[s] = lds[in0 + k * din];
+                        vo[s] = lds[out0 + (k - 1) * dout];
+                    }
+                    if (add) {
+                        c1[s] = acc1[acc0 + k * dacc];
+                        c2[s] = acc2[acc0 + k * dacc];
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + s;
+                if (k < L) {
+                    a += vi[s] - vo[s];
+                    b += __umul24(vi[s], vi[s]) - __umul24(vo[s], vo[s]);
+                    acc1[acc0 + k * dacc] = c1[s] + a;
+                    acc2[acc0 + k * dacc] = c2[s] + b;
+                }
+            }
+        }
+    };
+
+    // rows: the line of output (cx, cy) is staged row cy + r, columns cx .. cx + 2r;
+    // 128 walkers (32 rows x 4 segments of 32 outputs)
+    if (HV) {
+        if (tid < kGsTH * 4) {
+            const int cy = tid & (kGsTH - 1), cx0 = (tid >> 5) * 32;
+            const int row = (cy + r) * P + cx0;
+            walk(row, 1, row + w2, 1, row, 1, cy * kGsAccPitch + cx0, 1, 32, false);
+        }
+        __syncthreads();
+    }
+    if (DG) {
+        constexpr int ND = kGsTW + kGsTH - 1;  // diagonals crossing the tile
+        // diagonals: the line of (cx, cy) is staged (cy + t, cx + t), t = 0 .. 2r;
+        // walkers start on the top edge (tid < 128) or the left edge and move
+        // down and right
+        if (tid < ND) {
+            const int cx = tid < kGsTW ? tid : 0, cy = tid < kGsTW ? 0 : tid - kGsTW + 1;
+            const int L = imin(kGsTW - cx, kGsTH - cy);
+            const int c = cy * P + cx;
+            walk(c, P + 1, c + w2 * (P + 1), P + 1, c, P + 1, cy * kGsAccPitch + cx, kGsAccPitch + 1, L, HV);
+        }
+        __syncthreads();
+        // anti-diagonals: the line of (cx, cy) is staged (cy + t, cx + 2r - t);
+        // walkers start on the top edge (tid < 128) or the right edge and move
+        // down and left
+        if (tid < ND) {
+            const int cx = tid < kGsTW ? tid : kGsTW - 1, cy = tid < kGsTW ? 0 : tid - kGsTW + 1;
+            const int L = imin(cx + 1, kGsTH - cy);
+            const int c = cy * P + cx;
+            walk(c + w2, P - 1, c + w2 * P, P - 1, c + w2, P - 1, cy * kGsAccPitch + cx, kGsAccPitch - 1, L, true);
+        }
+        __syncthreads();
+    }
+
+    // columns and the decision: two walkers per column, 16 rows each; the
+    // column line of (cx, cy) is staged rows cy .. cy + 2r, column cx + r
     const int cx = tid & (kGsTW - 1);
     const int x = x0 + cx;
     if (x >= g.W) return;
-    const int P = g.pitch;
-    for (int cy = tid >> 7; cy < kGsTH; cy += kGsThreads / kGsTW) {
+    constexpr int kHalf = kGsTH / (kGsThreads / kGsTW);
+    const int cy0 = (tid / kGsTW) * kHalf;
+    const uint8_t *col = lds + cx + r;
+    uint32_t va = 0, vb = 0;
+    if (HV)
+        for (int t = 0; t <= w2; ++t) {
+            const uint32_t v = col[(cy0 + t) * P];
+            va += v;
+            vb += __umul24(v, v);
+        }
+    for (int cy = cy0; cy < cy0 + kHalf; ++cy) {
         const int y = y0 + cy;
         if (y >= g.H) break;
-        const uint8_t *c = lds + (cy + r) * P + (cx + r);  // the centre pixel
-        uint32_t a = 0, b = 0;
-        for (int t = -r; t <= r; ++t) {
-            if (ST != BZ_GS_X) {
-                const uint32_t v = c[t * P], h = c[t];
-                a += v + h;
-                b += __umul24(v, v) + __umul24(h, h);
-            }
-            if (ST != BZ_GS_PLUS) {
-                const uint32_t d = c[t * P + t], e = c[t * P - t];
-                a += d + e;
-                b += __umul24(d, d) + __umul24(e, e);
-            }
+        if (HV && cy > cy0) {
+            const uint32_t in = col[(cy + w2) * P], out = col[(cy - 1) * P];
+            va += in - out;
+            vb += __umul24(in, in) - __umul24(out, out);
         }
-        const uint32_t f = c[0];
+        const uint32_t f = col[(cy + r) * P];
+        const int i = cy * kGsAccPitch + cx;
         // every line passes through the centre: keep one copy of it
         const uint32_t extra = ST == BZ_GS_STAR ? 3u : 1u;
-        const uint32_t S1 = a - extra * f, S2 = b - extra * __umul24(f, f);
+        const uint32_t S1 = acc1[i] + va - extra * f, S2 = acc2[i] + vb - extra * __umul24(f, f);
         // in-image members of each line
         int cnt = 0;
-        if (ST != BZ_GS_X) {
+        if (HV) {
             const int nv = imin(y + r, g.H - 1) - imax(y - r, 0) + 1;
             const int nh = imin(x + r, g.W - 1) - imax(x - r, 0) + 1;
             cnt += nv + nh;
         }
-        if (ST != BZ_GS_PLUS) {
+        if (DG) {
             // (y + t, x + t) and (y + t, x - t) for |t| <= r
             const int nd = imin(imin(r, g.H - 1 - y), g.W - 1 - x) - imax(imax(-r, -y), -x) + 1;
             const int na = imin(imin(r, g.H - 1 - y), x) - imax(imax(-r, -y), x - (g.W - 1)) + 1;
@@ -126,13 +247,13 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
         float sq;
         const bool dark = RULE == BZ_SAUVOLA ? dark_sauvola(g.dec, f, S1, S2, n, sq)
                                              : dark_niblack(g.dec, f, S1, S2, n, sq);
-        const size_t i = (size_t)y * g.W + x;
-        g.out[i] = dark ? 0 : 255;
+        const size_t o = (size_t)y * g.W + x;
+        g.out[o] = dark ? 0 : 255;
         if (STATS) {
-            if (g.s1) g.s1[i] = S1;
-            if (g.s2) g.s2[i] = S2;
-            if (g.n) g.n[i] = n;
-            if (g.t) g.t[i] = threshold_value<RULE>(g.dec, S1, n, sq);
+            if (g.s1) g.s1[o] = S1;
+            if (g.s2) g.s2[o] = S2;
+            if (g.n) g.n[o] = n;
+            if (g.t) g.t[o] = threshold_value<RULE>(g.dec, S1, n, sq);
         }
     }
 }
