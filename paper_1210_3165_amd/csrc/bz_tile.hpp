@@ -281,7 +281,7 @@ __device__ __forceinline__ float threshold_value(const PageArgs &a, uint32_t S1,
     return RULE == 0 ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
 }
 
-// Interior Sauvola: true if f < t (output 0).
+// Whole-window Sauvola (per-tile constants): true if f < t (output 0).
 __device__ __forceinline__ bool dark_sauvola_row(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
                                                  const RowSauvola &q, float &sq) {
     sq = exact_sqrt_d(q.nd, S1, S2);
