@@ -209,6 +209,33 @@ def test_unaligned_buffers(bz, oracle_mod, offset):
         assert int(obuf[:offset + 3].sum()) == 0 and int(obuf[offset + 3 + H * W:].sum()) == 0
 
 
+@pytest.mark.parametrize("C", [1, 3])
+def test_aligned_input_any_output_offset(bz, oracle_mod, C):
+    """Input rows 16-byte aligned, output buffer at byte offsets 1..16: the
+    aligned body needs 8-byte-aligned output rows and otherwise the general
+    body runs; every offset gives the same bytes, matching the oracle, and
+    the bytes around the output stay untouched."""
+    from oracle.compare import compare_out
+    import pagegen
+    H, W = 150, 528  # W * C a multiple of 16
+    img = pagegen.page(H, W, pagegen.strokes_for(H, W), seed=31 + C, channels=C)
+    dimg = torch.from_numpy(img).cuda()
+    assert dimg.data_ptr() % 16 == 0
+    ref = oracle_mod.binarize(img, 31, f32(0.34), 128.0, 0)
+    first = None
+    for off in (16, 1, 2, 4, 8, 12):
+        obuf = torch.zeros(H * W + 64, dtype=torch.uint8, device="cuda")
+        out = obuf[off:off + H * W].view(H, W)
+        bz.binarize(dimg, 31, f32(0.34), 128.0, 0, out=out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert compare_out(got, ref.out, ref.gray, ref.t)["ok"], (C, off)
+        if first is None:
+            first = got
+        assert np.array_equal(got, first), (C, off)
+        assert int(obuf[:off].sum()) == 0 and int(obuf[off + H * W:].sum()) == 0, (C, off)
+
+
 @pytest.mark.parametrize("C,rule,win,k", [(1, 0, 15, 0.5), (1, 0, 31, 0.34), (1, 1, 31, -0.2), (1, 0, 61, 0.5),
                                           (3, 0, 31, 0.34), (3, 1, 15, -0.2), (1, 0, 101, 0.5)])
 def test_interior_tiles_full_compare(bz, oracle_mod, C, rule, win, k):
