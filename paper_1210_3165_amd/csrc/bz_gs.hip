@@ -62,9 +62,10 @@ struct GsArgs {
     PageArgs dec; // k, c1 = 1 - k, c2 = k / R' for the decision helpers
 };
 
-// Staged row pitch: at least the tile plus halo, and an odd number of words,
-// so that walkers on consecutive rows read different banks.
-__host__ __device__ inline int gs_pitch(int r) { return round_up(kGsTW + 2 * r, 8) + 4; }
+// Staged row pitch: the tile plus halo plus up to 15 columns of chunk
+// alignment and one chunk of slack, and an odd number of words, so that
+// walkers on consecutive rows read different banks.
+__host__ __device__ inline int gs_pitch(int r) { return round_up(kGsTW + 2 * r + 32, 8) + 4; }
 // Accumulator row pitch in words (odd for the same reason).
 constexpr int kGsAccPitch = kGsTW + 1;
 __host__ __device__ inline int gs_stage_bytes(int r) { return round_up((kGsTH + 2 * r) * gs_pitch(r), 16); }
@@ -82,41 +83,48 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
     const int x0 = tx * kGsTW, y0 = ty * kGsTH;
     const int r = g.r, rows = kGsTH + 2 * r, cols = kGsTW + 2 * r;
 
-    // stage the tile and its halo as gray levels (0 outside the image): the
-    // rows x cols pixels in row-major order, pixel i = tid + 256 j; each lane
-    // issues the loads of 8 pixels before storing any, so the staging waits
-    // for memory once per 2048 pixels instead of once per row (larger batches
-    // measured slower: the per-pixel address and bounds work dominates)
+    // stage the tile and its halo as gray levels (0 outside the image) in
+    // 16-pixel chunks starting on multiples of 16 image columns: LDS column 0
+    // holds image column xr0 = floor16(x0 - r), and staged column c (image
+    // column x0 - r + c) sits at LDS column off + c.  A job is one chunk of
+    // one row, fetched with word loads clamped to the row and reduced to gray
+    // levels by the tile kernel's helpers; each lane runs two jobs at a time.
+    const int xr0 = floor16(x0 - r), off = x0 - r - xr0;
     {
-        constexpr int kB = 8;
-        const int total = rows * cols;
-        const int dq = kGsThreads / cols, dr = kGsThreads - dq * cols;  // (row, col) step of 256 pixels
-        int ry = tid / cols, rx = tid - (tid / cols) * cols;
-        for (int i0 = tid; i0 < total; i0 += kB * kGsThreads) {
-            uint32_t v[kB];
-            int so[kB];  // LDS offset of pixel u
+        const int nq = (off + cols + 15) >> 4;  // chunks per staged row
+        const int jobs = rows * nq;
+        for (int j0 = tid; j0 < jobs; j0 += 2 * kGsThreads) {
+            RawChunk<C> k[2];
+            bool ok[2];
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                so[u] = ry * g.pitch + rx;
-                v[u] = 0u;
-                const int yy = y0 - r + ry, xx = x0 - r + rx;
-                if (i0 + u * kGsThreads < total && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) {
-                    const uint8_t *q = g.img + ((size_t)yy * g.W + xx) * C;
-                    v[u] = C == 1 ? (uint32_t)q[0] : gray_of(q[0], q[1], q[2]);
-                }
-                rx += dr;
-                ry += dq;
-                if (rx >= cols) {
-                    rx -= cols;
-                    ++ry;
+            for (int u = 0; u < 2; ++u) {
+                const int j = j0 + u * kGsThreads;
+                ok[u] = false;
+                if (j < jobs) {
+                    const int ry = j / nq, q = j - ry * nq, yy = y0 - r + ry;
+                    ok[u] = yy >= 0 && yy < g.H;
+                    const int yc = imin(imax(yy, 0), g.H - 1);
+                    fetch_chunk<C, false>(k[u], g.img + (size_t)yc * g.W * C, xr0 + 16 * q, g.W, true);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kB; ++u)
-                if (i0 + u * kGsThreads < total) lds[so[u]] = (uint8_t)v[u];
+            for (int u = 0; u < 2; ++u) {
+                const int j = j0 + u * kGsThreads;
+                if (j < jobs) {
+                    const int ry = j / nq, q = j - ry * nq;
+                    uint4 v = chunk_gray<C, false>(k[u], xr0 + 16 * q, g.W, true);
+                    if (!ok[u]) v = make_uint4(0u, 0u, 0u, 0u);
+                    uint32_t *d = reinterpret_cast<uint32_t *>(lds + ry * g.pitch + 16 * q);  // 4-byte aligned
+                    d[0] = v.x;
+                    d[1] = v.y;
+                    d[2] = v.z;
+                    d[3] = v.w;
+                }
+            }
         }
     }
     __syncthreads();
+    const uint8_t *stg = lds + off;  // staged column 0
 
     const int P = g.pitch, w2 = 2 * r;
     uint32_t *acc1 = reinterpret_cast<uint32_t *>(lds + gs_stage_bytes(r));  // [kGsTH][kGsAccPitch]
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
                     bool add) {
         uint32_t a = 0, b = 0;
         for (int t = 0; t <= w2; ++t) {
-            const uint32_t v = lds[first + t * step_first];
+            const uint32_t v = stg[first + t * step_first];
             a += v;
             b += __umul24(v, v);
         }
@@ -146,8 +154,8 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
                 vi[s] = vo[s] = c1[s] = c2[s] = 0u;
                 if (k < L) {
                     if (k > 0) {
-                        vi[s] = lds[in0 + k * din];
-                        vo[s] = lds[out0 + (k - 1) * dout];
+                        vi[s] = stg[in0 + k * din];
+                        vo[s] = stg[out0 + (k - 1) * dout];
                     }
                     if (add) {
                         c1[s] = acc1[acc0 + k * dacc];
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(kGsThreads) void bz_gs_kernel(const GsArgs g) {
     if (x >= g.W) return;
     constexpr int kHalf = kGsTH / (kGsThreads / kGsTW);
     const int cy0 = (tid / kGsTW) * kHalf;
-    const uint8_t *col = lds + cx + r;
+    const uint8_t *col = stg + cx + r;
     uint32_t va = 0, vb = 0;
     if (HV)
         for (int t = 0; t <= w2; ++t) {
