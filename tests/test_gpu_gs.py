@@ -82,6 +82,28 @@ def test_gs_constant_page(bz, oracle_mod):
         check(bz, oracle_mod, img, 9, 0.5, 128.0, structure)
 
 
+@pytest.mark.parametrize("offset", [1, 2, 3, 5, 13])
+def test_gs_unaligned_input(bz, oracle_mod, offset):
+    """Input at odd byte offsets and widths that are not a multiple of 4:
+    the staging fetches 16-pixel chunks with word loads clamped to each row,
+    so every alignment of the rows against the words must give the same
+    sums as the oracle."""
+    from oracle.compare import as_u32, compare_out
+    for C, (H, W) in ((1, (70, 301)), (3, (45, 203))):
+        img = pagegen.page(H, W, 60, seed=offset * 10 + C, channels=C)
+        buf = torch.zeros(img.size + 32, dtype=torch.uint8, device="cuda")
+        view = buf[offset:offset + img.size].view(*img.shape)
+        view.copy_(torch.from_numpy(img))
+        for structure in (PLUS, X, STAR):
+            ref = oracle_mod.binarize_gs(img, 15, f32(0.34), f32(128.0), structure)
+            g = bz.binarize_gs(view, 15, f32(0.34), f32(128.0), structure, stats=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(as_u32(g["s1"].cpu().numpy()), ref.s1), (offset, C, structure)
+            assert np.array_equal(as_u32(g["s2"].cpu().numpy()), ref.s2), (offset, C, structure)
+            rep = compare_out(g["out"].cpu().numpy(), ref.out, oracle_mod.gray(img), ref.t)
+            assert rep["ok"], (offset, C, structure, rep)
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("H,W,C,structure", [(4096, 4096, 1, STAR), (3508, 2480, 3, PLUS)])
 def test_gs_full_size(bz, oracle_mod, H, W, C, structure):
