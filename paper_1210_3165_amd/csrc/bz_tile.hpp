@@ -473,7 +473,16 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
-    const bool x_inside = X0 - lo >= 0 && X0 + TW - 1 + hi <= a.W - 1;
+    // Steps whose windows all span win rows, in a 256-column block of the
+    // page (counted from column 0) whose windows all span win columns, are
+    // decided with the per-tile Sauvola constants; every other pixel takes
+    // the per-pixel n form.  The two forms round differently, so the choice
+    // is made per 256-column block rather than per tile: a 128-column tile
+    // lies inside one block, and steps start on multiples of 8 image rows
+    // for every tile height, so the output bytes never depend on the tile
+    // shape.
+    const int XB = X0 & ~255;
+    const bool x_inside = XB - lo >= 0 && XB + 255 + hi <= a.W - 1;
     // steps whose windows are all whole: n = win^2, Sauvola constants per tile
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const RowSauvola q_full = row_sauvola(a, n_full);
@@ -582,7 +591,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
         float sqv[OPT];
-        if (x_inside && full_rows) {  // uniform: every window of the step is win x win
+        if (x_inside && full_rows) {  // uniform: every window of the step and block is win x win
             if (RULE == 0) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {

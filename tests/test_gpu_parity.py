@@ -186,6 +186,23 @@ def test_tile_shapes_bit_identical(bz, oracle_mod, tile):
     assert compare_out(out, ref.out, ref.gray, ref.t)["ok"]
 
 
+@pytest.mark.parametrize("C", [1, 3])
+def test_tile_shapes_identical_full_page(bz, C):
+    """A 4096-square page at four windows: 128- and 256-column tiles of
+    several heights give the same bytes.  The decision form is chosen per
+    256-column block of the page and per 8-row step, never per tile."""
+    import pagegen
+    img = torch.from_numpy(pagegen.page(4096, 4096, pagegen.strokes_for(4096, 4096), seed=11 + C,
+                                        channels=C)).cuda()
+    for win, k in ((15, 0.5), (31, 0.34), (61, 0.2), (101, 0.5)):
+        k = f32(k)
+        base = bz.binarize(img, win, k, 128.0, 0, tile=(256, 64))
+        for tile in ((128, 64), (256, 128), (128, 32), (256, 8)):
+            out = bz.binarize(img, win, k, 128.0, 0, tile=tile)
+            torch.cuda.synchronize()
+            assert torch.equal(out, base), (C, win, tile, int((out != base).sum()))
+
+
 @pytest.mark.parametrize("offset", [1, 2, 3, 5, 13])
 def test_unaligned_buffers(bz, oracle_mod, offset):
     """Image and output starting at odd byte offsets, widths not a multiple
