@@ -108,6 +108,27 @@ int binarize_tuned(const uint8_t *img, int H, int W_img, int channels, int win,
                    int tile_h, void *stream);
 
 /*
+ * binarize_staged -- as binarize_async, computed in two passes through HBM
+ * (the unfused form): a row pass writes the row window sums of f and f^2
+ * (Sec. 2) of every pixel to two u32 planes in the caller's workspace, and a
+ * column pass sums them down the window and decides (Eq. 3, Eq. 4 / Niblack).
+ * The output is identical, byte for byte, to binarize's.  It moves about
+ * 24 B/px more than binarize and exists so that the autotuner can measure
+ * pass fusion.
+ *   ws: device workspace of at least binarize_staged_workspace_size(H, W_img)
+ *       bytes (8 H W_img), 4-byte aligned, not overlapping img or out; its
+ *       contents are overwritten.  BZ_ERR_WORKSPACE if missing, too small or
+ *       misaligned; BZ_ERR_ALIAS on overlap; the other errors as binarize.
+ */
+int binarize_staged(const uint8_t *img, int H, int W_img, int channels,
+                    int win, float k, float R, int rule, uint8_t *out,
+                    uint32_t *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes binarize_staged needs for an H x W_img page (0 if the
+ * shape is invalid). */
+size_t binarize_staged_workspace_size(int H, int W_img);
+
+/*
  * binarize_stats -- as binarize_async, and also writes the intermediate
  * quantities of every pixel, each an H x W_img device plane (row pitch
  * W_img): gray (u8, Eq. 1), s1 and s2 (u32 window sums of f and f^2), n

@@ -17,7 +17,7 @@ import os
 import torch
 
 __all__ = [
-    "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats",
+    "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats", "binarize_staged",
     "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu",
     "binarize_gs", "fmeasure_counts", "GS_PLUS", "GS_X", "GS_STAR",
 ]
@@ -61,9 +61,12 @@ def lib() -> ctypes.CDLL:
     L.binarize_stats.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, vp, vp, vp, vp, vp]
     L.binarize_default_tile.argtypes = [i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
     L.binarize_tile_lds.argtypes = [i, i]
+    L.binarize_staged.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, ctypes.c_size_t, vp]
+    L.binarize_staged_workspace_size.argtypes = [i, i]
+    L.binarize_staged_workspace_size.restype = ctypes.c_size_t
     for name in ("binarize", "binarize_async", "binarize_tuned", "binarize_stats",
                  "binarize_default_tile", "binarize_version", "binarize_last_hip_error",
-                 "binarize_tile_lds"):
+                 "binarize_tile_lds", "binarize_staged"):
         getattr(L, name).restype = ctypes.c_int
     L.binarize_strerror.argtypes = [i]
     L.binarize_strerror.restype = ctypes.c_char_p
@@ -132,6 +135,34 @@ def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVO
                                   _ptr(out), int(tile[0]), int(tile[1]), s)
     if rc:
         raise BinarizeError(rc, "binarize")
+    return out
+
+
+def binarize_staged(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVOLA,
+                    out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                    stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """As ``binarize``, computed in two passes through HBM (row window sums
+    to two u32 planes, then the column pass and the decision).  Identical
+    bytes; slower.  ``workspace`` (optional) is a uint8 CUDA tensor of at
+    least 8*H*W bytes, allocated here when not given."""
+    H, W, C = _check_image(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
+            or not out.is_contiguous():
+        raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+    L = lib()
+    need = int(L.binarize_staged_workspace_size(H, W))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
+    elif workspace.device != img.device or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous tensor on the image's device")
+    with torch.cuda.device(img.device):
+        s = ctypes.c_void_p(_stream_ptr(stream, img.device))
+        rc = L.binarize_staged(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule), _ptr(out),
+                               _ptr(workspace), workspace.numel() * workspace.element_size(), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_staged")
     return out
 
 

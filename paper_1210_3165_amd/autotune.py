@@ -7,6 +7,10 @@ tuner is free to time candidates on random data of the real shapes.
 * ``Tuner.single_tile(H, W, C, win)`` picks (tile_w, tile_h) for one-page
   launches: the tile count must fill 256 CUs, yet taller tiles amortize the
   win start-up rows each tile spends before its first output.
+* ``Tuner.single(H, W, C, win)`` adds pass fusion to that choice: it times
+  the unfused, two-pass form (``binarize_staged``: row window sums through two
+  u32 planes in HBM, then the column pass) against the best fused tile, and
+  ``Tuner.binarize`` runs whichever won.  All choices give identical bytes.
 * ``Tuner.batch_config(specs)`` picks the persistent batch's LDS cap (2 or 4
   workgroups per CU) and tile height for a set of page shapes.
 
@@ -23,7 +27,7 @@ import threading
 
 import torch
 
-from . import Batch, binarize, tile_lds
+from . import Batch, binarize, binarize_staged, tile_lds
 
 WIN_BUCKETS = (15, 31, 61, 101, 151, 201, 255)
 SINGLE_TILES = ((256, 32), (256, 64), (256, 128), (256, 256), (128, 64), (128, 128), (128, 256))
@@ -121,6 +125,38 @@ class Tuner:
             self.cache[key] = {"tile": list(best), "ms": round(best_ms, 4), "tried": results}
             self._save()
         return best
+
+    def single(self, H: int, W: int, C: int, win: int, rule: int = 0) -> dict:
+        """{"fused": bool, "tile": [tw, th], "fused_ms", "staged_ms"} for one
+        page of this shape: the fused kernel at its best tile against the
+        staged two-pass form."""
+        tile = self.single_tile(H, W, C, win, rule)
+        key = f"{self.arch()}|fusion|C{C}|w{win_bucket(win)}|H{size_bucket(H)}|W{size_bucket(W)}"
+        with self._lock:
+            hit = self.cache.get(key)
+        if hit:
+            return dict(hit)
+        img = self._page(H, W, C)
+        out = torch.empty((H, W), dtype=torch.uint8, device=self.device)
+        ws = torch.empty(8 * H * W, dtype=torch.uint8, device=self.device)
+        fused_ms = self._time(lambda: binarize(img, win, 0.5, 128.0, rule, out=out, tile=tile))
+        staged_ms = self._time(lambda: binarize_staged(img, win, 0.5, 128.0, rule, out=out, workspace=ws))
+        rec = {"fused": fused_ms <= staged_ms, "tile": list(tile), "fused_ms": round(fused_ms, 4),
+               "staged_ms": round(staged_ms, 4)}
+        with self._lock:
+            self.cache[key] = rec
+            self._save()
+        return dict(rec)
+
+    def binarize(self, img: torch.Tensor, win: int, k: float, R: float = 128.0, rule: int = 0,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        """Binarize one page with the tuned choice of fusion and tile."""
+        H, W = img.shape[0], img.shape[1]
+        C = 1 if img.dim() == 2 else img.shape[2]
+        choice = self.single(H, W, C, win, rule)
+        if choice["fused"]:
+            return binarize(img, win, k, R, rule, out=out, tile=tuple(choice["tile"]))
+        return binarize_staged(img, win, k, R, rule, out=out)
 
     # ------------------------------------------------------------- batch
     def batch_config(self, specs) -> dict:

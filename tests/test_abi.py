@@ -189,3 +189,35 @@ def test_fmeasure_invalid_arguments(L, args, code):
     L.binarize_fmeasure_counts.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     a = [vp(x) if i != 2 else x for i, x in enumerate(args)]
     assert L.binarize_fmeasure_counts(*a, None) == code
+
+
+STAGED_WS = 8 * 16 * 16
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -1),            # null img
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, None, FAKE_WS, STAGED_WS), -1),             # null out
+    ((FAKE_IN, 0, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -2),          # H < 1
+    ((FAKE_IN, 16, 16, 2, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -3),         # two channels
+    ((FAKE_IN, 16, 16, 1, 256, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -4),        # window too wide
+    ((FAKE_IN, 16, 16, 1, 15, float("nan"), 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -5),
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 2, FAKE_OUT, FAKE_WS, STAGED_WS), -6),         # unknown rule
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, None, STAGED_WS), -10),           # no workspace
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS - 1), -10),    # too small
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS + 2, STAGED_WS), -10),    # misaligned
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_IN + 8, FAKE_WS, STAGED_WS), -7),      # out over img
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_IN + 200, STAGED_WS), -7),   # ws over img
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_OUT - 100, STAGED_WS), -7),  # ws over out
+])
+def test_staged_invalid_arguments(L, args, code):
+    vp, i, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+    L.binarize_staged.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, ctypes.c_size_t, vp]
+    a = [vp(x) if j in (0, 8, 9) else x for j, x in enumerate(args)]
+    assert L.binarize_staged(*a, None) == code
+
+
+def test_staged_workspace_size(L):
+    L.binarize_staged_workspace_size.restype = ctypes.c_size_t
+    L.binarize_staged_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    assert L.binarize_staged_workspace_size(4096, 4096) == 8 * 4096 * 4096
+    assert L.binarize_staged_workspace_size(0, 5) == 0

@@ -62,3 +62,22 @@ def test_tuned_shapes_are_bit_identical(tmp_path):
     for (im, win), d in zip(jobs, dev):
         assert np.array_equal(d[1].cpu().numpy(),
                               bz.binarize(torch.from_numpy(im).cuda(), win, 0.5).cpu().numpy())
+
+
+@pytest.mark.gpu
+def test_fusion_choice_is_measured_and_bit_identical(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_3165_amd as bz
+    import pagegen
+    tuner = autotune.Tuner(path=str(tmp_path / "t.json"), reps=2)
+    choice = tuner.single(600, 900, 3, 31)
+    assert choice["fused_ms"] > 0 and choice["staged_ms"] > 0
+    assert choice["fused"] == (choice["fused_ms"] <= choice["staged_ms"])
+    img = torch.from_numpy(pagegen.page(600, 900, 300, seed=6, channels=3)).cuda()
+    ref = bz.binarize(img, 31, 0.5)
+    assert torch.equal(tuner.binarize(img, 31, 0.5), ref)
+    assert torch.equal(bz.binarize_staged(img, 31, 0.5), ref)
+    again = autotune.Tuner(path=str(tmp_path / "t.json"), reps=2)
+    assert again.single(600, 900, 3, 31) == choice
