@@ -71,3 +71,15 @@ def test_otsu_at_max_size(bz, oracle_mod):
     assert (o.T, o.kstar) == (T, kstar)
     assert np.array_equal(o.hist.cpu().numpy().astype(np.uint32), hist)
     assert torch.equal(out, torch.from_numpy(ref_out).cuda())
+
+
+def test_staged_equals_fused_at_max_size(bz):
+    """The staged two-pass path on the largest gray page (a 17 GB plane
+    workspace, 8.4 M row-pass workgroups): identical bytes to the fused
+    kernel."""
+    H = W = 46340
+    img = torch.from_numpy(tiled(H, W, 1)).cuda()
+    fused = bz.binarize(img, 31, f32(0.34), 128.0, 0)
+    staged = bz.binarize_staged(img, 31, f32(0.34), 128.0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, staged)
