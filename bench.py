@@ -37,22 +37,42 @@ CASES = [  # (rule, win, k) of the 4096^2 workload
 RULE_NAME = {0: "sauvola", 1: "niblack"}
 DOMINANT = "bz_page_kernel<256, gray, sauvola>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bz_page_kernel_sauvola_gray_4096.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_bz_page_kernel_sauvola_gray_4096.json")
+# one VALU wave instruction per quad-cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 from paper_1210_3165_amd.build import kernel_source_sha  # noqa: E402
 
 
-def measured_traffic():
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def _current_record(path):
+    """A committed counter record, if it was taken on the current kernel
+    source; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != kernel_source_sha():
+    return rec if rec.get("source_sha") == kernel_source_sha() else None
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs."""
+    rec = _current_record(TRAFFIC_FILE)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def measured_valu(pixels: int, avg_launch_ms: float):
+    """VALU lane instructions per pixel from a committed SQ counter run, and
+    the issue rate they imply at the measured launch time, against one VALU
+    wave instruction per quad-cycle on every SIMD."""
+    rec = _current_record(VALU_FILE)
+    if not rec or not rec.get("valu_lane_ops_per_px"):
         return None
-    return rec.get("bytes_per_launch")
+    ops = float(rec["valu_lane_ops_per_px"])
+    rate = ops * pixels / (avg_launch_ms * 1e-3)
+    return {"lane_ops_per_px": ops, "achieved_T_lane_ops_s": rate / 1e12,
+            "peak_T_lane_ops_s": VALU_PEAK_LANE_OPS / 1e12, "frac": rate / VALU_PEAK_LANE_OPS}
 
 
 def _f32(x: float) -> float:
@@ -458,6 +478,7 @@ def main() -> int:
             "kernel": DOMINANT,
             "bytes_per_launch": 2 * px,
             "avg_launch_ms": avg_ms,
+            "valu": measured_valu(px, avg_ms),
         },
         "cases": cases,
         "copy_GBps": copy_gbps,

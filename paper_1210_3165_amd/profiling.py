@@ -9,6 +9,10 @@
     # in the same process (16 MiB each way)
     python -m paper_1210_3165_amd.profiling traffic FETCH_CSV WRITE_CSV --kernel SUBSTR ...
 
+    # instruction mix per dispatch from one SQ counter run (SQ_INSTS_VALU and
+    # friends count wave instructions; x64 gives lane instructions)
+    python -m paper_1210_3165_amd.profiling valu SQ_CSV --kernel SUBSTR --pixels N ...
+
 Only reads CSV files; runs nothing on the GPU.
 """
 from __future__ import annotations
@@ -129,6 +133,40 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, worklo
     }
 
 
+# Counters of the instruction-mix record; SQ_INSTS_VALU is required.
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
+
+
+def valu(sq_csv: str, kernel: str, pixels: int, workload: str, commands: list[str],
+         sources: tuple[str, ...]) -> dict:
+    """Mean instruction counts per dispatch of the kernels whose name contains
+    `kernel`, and VALU lane instructions per output pixel (wave instructions
+    x 64 lanes / pixels per dispatch)."""
+    if pixels <= 0:
+        raise SystemExit("pixels per dispatch must be positive")
+    name, means = None, {}
+    for c in SQ_COUNTERS:
+        vals = []
+        for (n, _), vs in _counter(sq_csv, c).items():
+            if kernel in n:
+                vals += vs
+                name = n
+        if vals:
+            means[c] = statistics.mean(vals)
+    if "SQ_INSTS_VALU" not in means:
+        raise SystemExit(f"no SQ_INSTS_VALU rows for a kernel matching {kernel!r}")
+    return {
+        "kernel": name,
+        "workload": workload,
+        "source_sha": kernel_source_sha(sources),
+        "pixels_per_dispatch": pixels,
+        "per_dispatch": {c: round(v, 1) for c, v in means.items()},
+        "valu_lane_ops_per_px": round(means["SQ_INSTS_VALU"] * 64 / pixels, 3),
+        "commands": commands,
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -146,9 +184,19 @@ def main(argv=None) -> int:
     f.add_argument("--workload", required=True)
     f.add_argument("--command", action="append", default=[])
     f.add_argument("--sources", default="binarize.hip,bz_common.hpp,bz_tile.hpp")
+    v = sub.add_parser("valu")
+    v.add_argument("sq_csv")
+    v.add_argument("--kernel", required=True, help="substring of the kernel name")
+    v.add_argument("--pixels", type=int, required=True, help="output pixels per dispatch")
+    v.add_argument("--workload", required=True)
+    v.add_argument("--command", action="append", default=[])
+    v.add_argument("--sources", default="binarize.hip,bz_common.hpp,bz_tile.hpp")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         sys.stdout.write(trace_summary(a.dir, a.prefix, a.title, a.command, a.note))
+    elif a.cmd == "valu":
+        rec = valu(a.sq_csv, a.kernel, a.pixels, a.workload, a.command, tuple(a.sources.split(",")))
+        sys.stdout.write(json.dumps(rec, indent=1) + "\n")
     else:
         rec = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.workload, a.command,
                       tuple(a.sources.split(",")))

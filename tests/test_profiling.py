@@ -1,0 +1,77 @@
+"""Host logic that turns rocprofv3 counter CSVs into the committed profile
+records, and the bench's use of those records (no GPU involved)."""
+import csv
+import json
+
+import pytest
+
+import bench
+from paper_1210_3165_amd import profiling
+from paper_1210_3165_amd.build import kernel_source_sha
+
+KERNEL = "void bz::bz_page_kernel<256, 1, 0, false>(bz::PageArgs)"
+OTHER = "void bz::bz_page_kernel<256, 1, 1, false>(bz::PageArgs)"
+
+
+def write_csv(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"], r)))
+
+
+def test_traffic_scales_by_the_copy_kernel(tmp_path):
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    copy = profiling.COPY_KERNEL
+    # the copy moves 16 MiB each way; its counters read 8192 KiB fetched and
+    # 16384 KiB written, so fetch counts are scaled by 2 and writes by 1
+    write_csv(f, [(copy, 1, "FETCH_SIZE", 8192.0), (copy, 1, "FETCH_SIZE", 8192.0),
+                  (KERNEL, 262144, "FETCH_SIZE", 9000.0), (KERNEL, 131072, "FETCH_SIZE", 10000.0),
+                  (OTHER, 262144, "FETCH_SIZE", 1.0)])
+    write_csv(w, [(copy, 1, "WRITE_SIZE", 16384.0), (KERNEL, 262144, "WRITE_SIZE", 16384.0),
+                  (KERNEL, 131072, "WRITE_SIZE", 16384.0)])
+    rec = profiling.traffic(str(f), str(w), "<256, 1, 0, false>", 16 * 2**20, "w", ["cmd"],
+                            ("bz_tile.hpp",))
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["bytes_per_launch"] == int((9500.0 * 2 + 16384.0) * 1024)
+    assert rec["per_grid_fetch_kib_raw"] == {"131072": 10000.0, "262144": 9000.0}
+    assert rec["source_sha"] == kernel_source_sha(("bz_tile.hpp",))
+
+
+def test_traffic_needs_copy_and_kernel_rows(tmp_path):
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_csv(f, [(KERNEL, 1, "FETCH_SIZE", 1.0)])
+    write_csv(w, [(KERNEL, 1, "WRITE_SIZE", 1.0)])
+    with pytest.raises(SystemExit):
+        profiling.traffic(str(f), str(w), "bz_page", 16 * 2**20, "w", [], ("bz_tile.hpp",))
+
+
+def test_valu_lane_ops_per_pixel(tmp_path):
+    p = tmp_path / "sq.csv"
+    px = 4096 * 4096
+    write_csv(p, [(KERNEL, 262144, "SQ_INSTS_VALU", 10_000_000.0), (KERNEL, 131072, "SQ_INSTS_VALU", 12_000_000.0),
+                  (KERNEL, 262144, "SQ_WAVES", 4096.0), (KERNEL, 131072, "SQ_WAVES", 2048.0),
+                  (OTHER, 262144, "SQ_INSTS_VALU", 1.0)])
+    rec = profiling.valu(str(p), "<256, 1, 0, false>", px, "w", ["cmd"], ("bz_tile.hpp",))
+    assert rec["kernel"] == KERNEL
+    assert rec["per_dispatch"] == {"SQ_WAVES": 3072.0, "SQ_INSTS_VALU": 11_000_000.0}
+    assert rec["valu_lane_ops_per_px"] == round(11_000_000 * 64 / px, 3)
+    with pytest.raises(SystemExit):
+        profiling.valu(str(p), "no such kernel", px, "w", [], ("bz_tile.hpp",))
+
+
+def test_bench_uses_records_of_the_current_source_only(tmp_path, monkeypatch):
+    rec = {"source_sha": kernel_source_sha(), "valu_lane_ops_per_px": 40.0, "bytes_per_launch": 123}
+    path = tmp_path / "r.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "VALU_FILE", str(path))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    px, ms = 4096 * 4096, 0.04
+    v = bench.measured_valu(px, ms)
+    assert v["lane_ops_per_px"] == 40.0
+    assert v["peak_T_lane_ops_s"] == pytest.approx(39.3216)
+    assert v["frac"] == pytest.approx(40.0 * px / 40e-6 / 39.3216e12)
+    assert bench.measured_traffic() == 123
+    path.write_text(json.dumps(dict(rec, source_sha="0" * 64)))
+    assert bench.measured_valu(px, ms) is None and bench.measured_traffic() is None
