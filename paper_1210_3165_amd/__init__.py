@@ -109,6 +109,17 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _keep_for(stream, device, *tensors) -> None:
+    """Tensors allocated here come from the current stream's pool; when the
+    work runs on another stream, tell the allocator so that it does not hand
+    their memory out again before that stream has finished with it."""
+    if stream is None or stream == torch.cuda.current_stream(device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVOLA,
              out: torch.Tensor | None = None, tile: tuple[int, int] | None = None,
              stream: torch.cuda.Stream | None = None) -> torch.Tensor:
@@ -121,6 +132,7 @@ def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVO
     H, W, C = _check_image(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+        _keep_for(stream, img.device, out)
     elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
             or not out.is_contiguous():
         raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
@@ -148,6 +160,7 @@ def binarize_staged(img: torch.Tensor, win: int, k: float, R: float = 128.0, rul
     H, W, C = _check_image(img)
     if out is None:
         out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+        _keep_for(stream, img.device, out)
     elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
             or not out.is_contiguous():
         raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
@@ -155,6 +168,7 @@ def binarize_staged(img: torch.Tensor, win: int, k: float, R: float = 128.0, rul
     need = int(L.binarize_staged_workspace_size(H, W))
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
+        _keep_for(stream, img.device, workspace)
     elif workspace.device != img.device or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous tensor on the image's device")
     with torch.cuda.device(img.device):
@@ -180,6 +194,7 @@ def binarize_stats(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule
         "n": torch.empty((H, W), dtype=torch.int32, device=dev),
         "t": torch.empty((H, W), dtype=torch.float32, device=dev),
     }
+    _keep_for(stream, dev, *res.values())
     L = lib()
     with torch.cuda.device(dev):
         s = ctypes.c_void_p(_stream_ptr(stream, dev))
@@ -330,13 +345,21 @@ class Otsu:
     """Otsu's global threshold (``binarize_otsu`` in the C ABI) with its own
     device workspace.  ``run`` enqueues the histogram, the selection of T and
     (unless ``threshold_only``) the Eq. 2 decision on the stream; afterwards
-    ``hist``, ``T`` and ``kstar`` read the workspace (``T``/``kstar`` sync).
+    ``hist``, ``T`` and ``kstar`` read the workspace (``T``/``kstar`` sync;
+    all three first order the current stream after the last run's stream).
     Calls on one object must be ordered (one stream, or synchronised)."""
 
     def __init__(self, device=None):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         _otsu_lib()
         self.ws = torch.empty(OTSU_WS_WORDS, dtype=torch.int32, device=self.device)
+        self._last_stream = None
+
+    def _ws_view(self, lo: int, hi: int) -> torch.Tensor:
+        cur = torch.cuda.current_stream(self.device)
+        if self._last_stream is not None and self._last_stream != cur:
+            cur.wait_stream(self._last_stream)
+        return self.ws[lo:hi]
 
     def run(self, img: torch.Tensor, out: torch.Tensor | None = None, threshold_only: bool = False,
             stream: torch.cuda.Stream | None = None) -> torch.Tensor | None:
@@ -347,29 +370,32 @@ class Otsu:
             out = None
         elif out is None:
             out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+            _keep_for(stream, img.device, out)
         elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
                 or not out.is_contiguous():
             raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+        _keep_for(stream, self.device, self.ws)
         with torch.cuda.device(self.device):
             s = ctypes.c_void_p(_stream_ptr(stream, self.device))
             rc = _otsu_lib().binarize_otsu(_ptr(img), H, W, C, _ptr(out), _ptr(self.ws),
                                            4 * OTSU_WS_WORDS, s)
         if rc:
             raise BinarizeError(rc, "binarize_otsu")
+        self._last_stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         return out
 
     @property
     def hist(self) -> torch.Tensor:
         """Histogram of the last run's gray levels (256 counts, device)."""
-        return self.ws[OTSU_WS_HIST:OTSU_WS_HIST + 256]
+        return self._ws_view(OTSU_WS_HIST, OTSU_WS_HIST + 256)
 
     @property
     def T(self) -> int:
-        return int(self.ws[OTSU_WS_T].item())
+        return int(self._ws_view(OTSU_WS_T, OTSU_WS_T + 1).item())
 
     @property
     def kstar(self) -> int:
-        return int(self.ws[OTSU_WS_KSTAR].item())
+        return int(self._ws_view(OTSU_WS_KSTAR, OTSU_WS_KSTAR + 1).item())
 
 
 def otsu(img: torch.Tensor, out: torch.Tensor | None = None,
@@ -420,12 +446,14 @@ def binarize_gs(img: torch.Tensor, win: int, k: float, Rp: float = 128.0, struct
     dev = img.device
     if out is None:
         out = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        _keep_for(stream, dev, out)
     elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != dev or not out.is_contiguous():
         raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
     planes = {}
     if stats:
         for name, dt in (("s1", torch.int32), ("s2", torch.int32), ("n", torch.int32), ("t", torch.float32)):
             planes[name] = torch.empty((H, W), dtype=dt, device=dev)
+        _keep_for(stream, dev, *planes.values())
     with torch.cuda.device(dev):
         s = ctypes.c_void_p(_stream_ptr(stream, dev))
         rc = _gs_lib().binarize_gs(_ptr(img), H, W, C, int(win), float(k), float(Rp), _structure(structure),
@@ -452,6 +480,7 @@ def fmeasure_counts(out: torch.Tensor, gt: torch.Tensor, counts: torch.Tensor | 
         raise ValueError("out and gt must have the same size and device")
     if counts is None:
         counts = torch.empty(3, dtype=torch.int64, device=out.device)
+        _keep_for(stream, out.device, counts)
     with torch.cuda.device(out.device):
         s = ctypes.c_void_p(_stream_ptr(stream, out.device))
         rc = _gs_lib().binarize_fmeasure_counts(_ptr(out), _ptr(gt), out.numel(), _ptr(counts), s)

@@ -306,6 +306,12 @@ class _GpuBase:
         self.t0_event.synchronize()
         self.t0 = clock.now()
 
+    def _begin(self, slot):
+        """Order the slot's stream after the current stream, where callers
+        usually produce the request tensors (e.g. a non-blocking upload), so
+        no kernel of the slot reads a page before it is written."""
+        self.streams[slot].wait_stream(self.torch.cuda.current_stream(self.device))
+
     def _outs(self, slot, batch):
         bufs = []
         for r in batch:
@@ -347,6 +353,7 @@ class GpuBatchExecutor(_GpuBase):
         self.batches = [Batch(max_pages, lds_cap=lds_cap, device=self.device) for _ in range(slots)]
 
     def submit(self, slot, batch, now):
+        self._begin(slot)
         self._outs(slot, batch)
         if len(batch) == 1:
             from . import binarize
@@ -368,6 +375,7 @@ class GpuSingleExecutor(_GpuBase):
 
     def submit(self, slot, batch, now):
         from . import binarize
+        self._begin(slot)
         self._outs(slot, batch)
         for r in batch:
             binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
@@ -392,6 +400,7 @@ class GpuHostBatchExecutor(GpuBatchExecutor):
     def submit(self, slot, batch, now):
         torch = self.torch
         st = self.streams[slot]
+        self._begin(slot)
         dev_bufs, host_bufs, jobs = [], [], []
         with torch.cuda.stream(st):
             for r in batch:
