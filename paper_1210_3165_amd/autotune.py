@@ -64,7 +64,8 @@ class Tuner:
     def __init__(self, path: str | None = None, reps: int = 8, device=None):
         self.path = path or default_cache_path()
         self.reps = reps
-        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.device = torch.device(device) if device is not None else \
+            torch.device("cuda", torch.cuda.current_device())
         self._lock = threading.Lock()
         self.cache = self._load()
 
@@ -77,8 +78,14 @@ class Tuner:
             return {}
 
     def _save(self) -> None:
+        """Merge this tuner's entries into the file on disk (entries other
+        processes saved meanwhile are kept) and replace it atomically through
+        a temporary file of this process and thread."""
         os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
-        tmp = self.path + ".tmp"
+        merged = self._load()
+        merged.update(self.cache)
+        self.cache = merged
+        tmp = f"{self.path}.{os.getpid()}.{threading.get_ident()}.tmp"
         with open(tmp, "w") as fh:
             json.dump(self.cache, fh, indent=1, sort_keys=True)
         os.replace(tmp, self.path)

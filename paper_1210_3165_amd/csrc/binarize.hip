@@ -2,6 +2,7 @@
 // planning, kernel dispatch and the C ABI declared in include/binarize.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <mutex>
@@ -43,22 +44,19 @@ int validate(const uint8_t *img, int H, int W, int C, int win, float k, float R,
     return BZ_OK;
 }
 
-// Compute units of the current device (cached per device id).
+// Compute units of the current device (cached per device id; threads that
+// race on the first query store the same value).
 int device_cus() {
-    static std::once_flag once;
-    static int cus[64];
-    std::call_once(once, [] {
-        for (int i = 0; i < 64; ++i) cus[i] = 0;
-    });
+    static std::atomic<int> cus[64];  // zero-initialised: not yet queried
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cus[dev] == 0) {
-        int v = 0;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
             v = 256;
-        cus[dev] = v;
+        cus[dev].store(v, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return v;
 }
 
 void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
@@ -122,8 +120,8 @@ void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int C, int win, fl
 template <int TW, int C, int RULE, bool STATS>
 int launch_t(const PageArgs &a, int lds, hipStream_t st) {
     auto kern = bz_page_kernel<TW, C, RULE, STATS>;
-    static std::once_flag once;
-    std::call_once(once, [&] {
+    static std::once_flag once[kMaxDevices];
+    once_per_device(once, [&] {
         // allow the full 160 KB of gfx950 LDS for dynamic shared memory
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
         (void)hipGetLastError();

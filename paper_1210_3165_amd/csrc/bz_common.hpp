@@ -4,6 +4,13 @@
 #include <stdint.h>
 
 #if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <utility>
+#endif
+
+#if defined(__HIPCC__)
 #define BZ_HD __host__ __device__
 #else
 #define BZ_HD
@@ -99,6 +106,23 @@ BZ_HD inline int v2_pos(int x, int width) {
 // HIP error of the last failed runtime call on this thread (kept by the
 // single-page entry points and the batch entry points alike).
 void set_last_hip_error(int e);
+
+#if defined(__HIPCC__)
+// Runs f once per device id (the current device): function attributes such
+// as the dynamic LDS limit belong to a device, so each device a process
+// launches on needs its own first call.
+constexpr int kMaxDevices = 64;
+template <class F>
+inline void once_per_device(std::once_flag (&flags)[kMaxDevices], F &&f) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        f();
+        return;
+    }
+    std::call_once(flags[dev], std::forward<F>(f));
+}
+#endif
 
 // Does this tile configuration fit the hardware?
 inline bool tile_fits(int tile_w, int win) {

@@ -342,8 +342,8 @@ int device_cus() {
 template <int C, int ST, int RULE, bool STATS>
 int gs_launch(const GsArgs &g, hipStream_t st) {
     auto kern = bz_gs_kernel<C, ST, RULE, STATS>;
-    static std::once_flag once;
-    std::call_once(once, [&] {
+    static std::once_flag once[kMaxDevices];
+    once_per_device(once, [&] {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
         (void)hipGetLastError();
     });

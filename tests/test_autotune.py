@@ -34,6 +34,27 @@ def test_cache_round_trip(tmp_path):
     assert t._load() == t.cache
 
 
+def test_cache_saves_merge_entries_of_other_tuners(tmp_path):
+    """Two tuners on one cache file (say two processes): each save keeps the
+    entries the other saved meanwhile, and no temporary file is left."""
+    import threading
+    path = str(tmp_path / "tune.json")
+    a, b = (autotune.Tuner.__new__(autotune.Tuner) for _ in range(2))
+    for t in (a, b):
+        t.path, t.reps, t._lock = path, 1, threading.Lock()
+        t.cache = t._load()
+    a.cache["k_a"] = {"tile": [256, 64]}
+    a._save()
+    b.cache["k_b"] = {"tile": [128, 64]}  # b loaded before a saved
+    b._save()
+    on_disk = json.loads(open(path).read())
+    assert set(on_disk) == {"k_a", "k_b"}
+    a.cache["k_a2"] = {"tile": [256, 128]}
+    a._save()
+    assert set(json.loads(open(path).read())) == {"k_a", "k_b", "k_a2"}
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["tune.json"]
+
+
 @pytest.mark.gpu
 def test_tuned_shapes_are_bit_identical(tmp_path):
     torch = pytest.importorskip("torch")
