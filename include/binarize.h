@@ -158,7 +158,9 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
  *   Waits for the previous run of the same object before rewriting its
  *   table.  Every img/out pointer must stay valid until the stream reaches
  *   the end of the run.  Errors as for binarize (per page), BZ_ERR_SHAPE for
- *   n_pages outside [1, max_pages].
+ *   n_pages outside [1, max_pages], BZ_ERR_ALIAS when a page's output
+ *   overlaps another page's output or any page's input (the pages run
+ *   concurrently; inputs may be shared).
  * binarize_batch_info -- persistent grid size, LDS cap, items of last run.
  * binarize_batch_destroy -- wait for the last run, free everything.
  */

@@ -10,10 +10,13 @@
 // not depend on which tile, launch or neighbour page it is computed with.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "binarize.h"
 #include "bz_common.hpp"
@@ -135,6 +138,31 @@ int check_page(const bz_page &p) {
     return BZ_OK;
 }
 
+// The pages of a batch run concurrently, so no output may overlap another
+// page's output or any page's input (inputs may overlap each other: they
+// are only read).  Sorting the output ranges makes this O(n log n).
+int check_cross_alias(const bz_page *pages, int n) {
+    std::vector<std::pair<uintptr_t, uintptr_t>> outs;  // [begin, end)
+    outs.reserve((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const uintptr_t o = (uintptr_t)pages[i].out;
+        outs.emplace_back(o, o + (size_t)pages[i].H * pages[i].W_img);
+    }
+    std::sort(outs.begin(), outs.end());
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].first < outs[i - 1].second) return BZ_ERR_ALIAS;
+    // disjoint and sorted: ends ascend too, so the first output ending after
+    // an input's start is the only candidate for overlapping it
+    for (int i = 0; i < n; ++i) {
+        const uintptr_t a = (uintptr_t)pages[i].img;
+        const uintptr_t b = a + (size_t)pages[i].H * pages[i].W_img * pages[i].channels;
+        auto it = std::upper_bound(outs.begin(), outs.end(), a,
+                                   [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &r) { return v < r.second; });
+        if (it != outs.end() && it->first < b) return BZ_ERR_ALIAS;
+    }
+    return BZ_OK;
+}
+
 // Tile for one page within the batch's LDS cap: the caller's choice if it
 // fits, else 256 columns when the window allows, else 128; tile_h 128 unless
 // given.
@@ -170,6 +198,7 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, int *items, int *m
         const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;  // t = m either way
         kinds[(tw == 256) * 4 + (p.channels == 3) * 2 + rule]++;
     }
+    if (int rc = check_cross_alias(pages, n)) return rc;
     int start[kKinds], fill[kKinds];
     for (int q = 0, acc = 0; q < kKinds; ++q) {
         start[q] = fill[q] = acc;

@@ -116,3 +116,32 @@ def test_batch_rejects_bad_pages(bz):
         B.run([(img, out, 15, 0.5, 128.0, 0)])  # still usable after errors
         torch.cuda.synchronize()
         assert torch.all(out == 255)
+
+
+def test_batch_rejects_pages_that_write_over_each_other(bz):
+    """Pages of a batch run concurrently: an output shared by two pages, or
+    one page's output inside another page's input, is refused before any
+    launch; shared inputs and outputs packed back to back are fine."""
+    import pagegen
+    a = torch.from_numpy(pagegen.page(40, 50, 30, seed=11)).cuda()
+    b = torch.from_numpy(pagegen.page(40, 50, 30, seed=12)).cuda()
+    buf = torch.zeros(3 * 40 * 50, dtype=torch.uint8, device="cuda")
+    o0, o1 = buf[:2000].view(40, 50), buf[2000:4000].view(40, 50)
+    rgb = torch.from_numpy(pagegen.page(40, 50, 30, seed=13, channels=3)).cuda()  # 6000 bytes
+    with bz.Batch(4) as B:
+        cases = [
+            [(a, o0, 15, 0.5, 128.0, 0), (b, o0, 15, 0.5, 128.0, 0)],                    # same output
+            [(a, o0, 15, 0.5, 128.0, 0), (b, buf[1999:3999].view(40, 50), 15, 0.5, 128.0, 0)],  # one byte shared
+            [(rgb, o0, 15, 0.5, 128.0, 0),
+             (a, rgb.view(-1)[1000:3000].view(40, 50), 15, 0.5, 128.0, 0)],              # output inside an RGB input
+        ]
+        for jobs in cases:
+            with pytest.raises(bz.BinarizeError) as ei:
+                B.run(jobs)
+            assert ei.value.code == -7
+        # a shared input and outputs packed back to back
+        B.run([(a, o0, 15, 0.5, 128.0, 0), (a, o1, 31, -0.2, 128.0, 1), (b, buf[4000:].view(40, 50), 61, 0.3, 128.0, 0)])
+        torch.cuda.synchronize()
+        assert torch.equal(o0, bz.binarize(a, 15, 0.5, 128.0, 0))
+        assert torch.equal(o1, bz.binarize(a, 31, -0.2, 128.0, 1))
+        assert torch.equal(buf[4000:].view(40, 50), bz.binarize(b, 61, 0.3, 128.0, 0))
