@@ -75,3 +75,16 @@ def test_bench_uses_records_of_the_current_source_only(tmp_path, monkeypatch):
     assert bench.measured_traffic() == 123
     path.write_text(json.dumps(dict(rec, source_sha="0" * 64)))
     assert bench.measured_valu(px, ms) is None and bench.measured_traffic() is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; asked for more it exits with a message and
+    without touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for extra, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *extra], capture_output=True,
+                           text=True, timeout=120, env={**os.environ, **env})
+        assert r.returncode == 2 and "one GPU only" in r.stderr, (extra, env, r.stderr)
