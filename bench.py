@@ -328,6 +328,45 @@ def run_gs_workload(reps: int) -> dict:
     return {"workload": "gs", "H": S, "W": S, "reps": reps, "runs": rows}
 
 
+def run_fusion_workload(reps: int) -> dict:
+    """Pass fusion on 4096^2 pages, gray and RGB: the fused tile kernel (one
+    pass) against the staged form (row window sums to two u32 planes, then the
+    column pass), Sauvola k=0.5 per window; microseconds per page from HIP
+    events, and whether the two outputs are identical."""
+    import torch
+
+    import pagegen
+    import paper_1210_3165_amd as bz
+    dev = torch.device("cuda:0")
+    S = 4096
+    pages = {1: pagegen.config1(size=S)[0].img,
+             3: pagegen.page(S, S, pagegen.strokes_for(S, S), seed=3000, channels=3)}
+    ws = torch.empty(8 * S * S, dtype=torch.uint8, device=dev)
+    o1 = torch.empty((S, S), dtype=torch.uint8, device=dev)
+    o2 = torch.empty((S, S), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    rows = []
+    for C, host in pages.items():
+        img = torch.from_numpy(host).to(dev)
+        for win in (15, 31, 61, 101):
+            fused = timed(lambda: bz.binarize(img, win, 0.5, 128.0, out=o1))
+            staged = timed(lambda: bz.binarize_staged(img, win, 0.5, 128.0, out=o2, workspace=ws))
+            rows.append({"channels": C, "win": win, "fused_us": fused, "staged_us": staged,
+                         "identical": bool(torch.equal(o1, o2))})
+    return {"workload": "fusion", "H": S, "W": S, "reps": reps, "runs": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,7 +380,7 @@ def main() -> int:
                     help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
     ap.add_argument("--workload", default="page4096",
-                    choices=["page4096", "batch-rgb", "batch-mixed", "serve", "otsu", "gs"],
+                    choices=["page4096", "batch-rgb", "batch-mixed", "serve", "otsu", "gs", "fusion"],
                     help="page4096: the metric line; batch-*: per-image vs persistent batch; "
                          "serve: continuous batching vs one launch per request; "
                          "otsu: the global-threshold baseline; gs: exact vs sampled window")
@@ -376,6 +415,9 @@ def main() -> int:
         return 0
     if args.workload == "gs":
         print(json.dumps(run_gs_workload(max(5, args.steps // 20))), flush=True)
+        return 0
+    if args.workload == "fusion":
+        print(json.dumps(run_fusion_workload(max(5, args.steps // 20))), flush=True)
         return 0
     if args.workload == "otsu":
         print(json.dumps(run_otsu_workload(max(10, args.steps), args.pool_mb)), flush=True)
