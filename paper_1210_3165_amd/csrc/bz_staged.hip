@@ -9,8 +9,8 @@
 //               R1 = sum f and R2 = sum f^2 over columns [x - lo, x + hi] of
 //               every pixel to two u32 planes of the caller's workspace.
 //   bz_colsum   one lane per column slides the window down 64 rows of those
-//               planes (S = S + R(y + hi) - R(y - lo - 1)) and decides with the
-//               fused kernel's helpers.
+//               planes (S = S + R(y + hi) - R(y - lo - 1)), loading 8 rows'
+//               entries at a time, and decides with the fused kernel's helpers.
 //
 // The decision form follows the fused kernel's rule exactly: pixels in a
 // 256-column block of the page whose windows all span win columns, in an
@@ -35,6 +35,7 @@ using namespace bz;
 
 constexpr int kSegW = 256;    // outputs per row-pass workgroup (one per lane)
 constexpr int kColTH = 64;    // rows per column-pass workgroup
+constexpr int kColGroup = 8;  // rows whose loads the column pass issues together
 constexpr int kStagedThreads = 256;
 
 struct StagedArgs {
@@ -123,29 +124,44 @@ __global__ __launch_bounds__(kStagedThreads) void bz_colsum(const StagedArgs s) 
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const RowSauvola q_full = row_sauvola(s.dec, n_full);
     const int Yend = min(Y0 + kColTH, H);
-    for (int y = Y0; y < Yend; ++y) {
-        if (y > Y0) {
-            if (y + hi <= H - 1) {
-                S1 += c1[(size_t)(y + hi) * W];
-                S2 += c2[(size_t)(y + hi) * W];
-            }
-            if (y - lo - 1 >= 0) {
-                S1 -= c1[(size_t)(y - lo - 1) * W];
-                S2 -= c2[(size_t)(y - lo - 1) * W];
-            }
+    // Rows go in groups of kColGroup: the entering and leaving plane entries
+    // and the gray levels of a whole group are loaded before any is used, so
+    // the loads are in flight together instead of one latency per row.
+    // Entries outside the image (and the first row's, already in the initial
+    // sum) read as zero.
+    for (int yg = Y0; yg < Yend; yg += kColGroup) {
+        uint32_t e1[kColGroup], e2[kColGroup], l1[kColGroup], l2[kColGroup], f[kColGroup];
+#pragma unroll
+        for (int i = 0; i < kColGroup; ++i) {
+            const int y = yg + i;
+            const bool row = y < Yend;
+            const bool enter = row && y > Y0 && y + hi <= H - 1;
+            const bool leave = row && y > Y0 && y - lo - 1 >= 0;
+            e1[i] = enter ? c1[(size_t)(y + hi) * W] : 0u;
+            e2[i] = enter ? c2[(size_t)(y + hi) * W] : 0u;
+            l1[i] = leave ? c1[(size_t)(y - lo - 1) * W] : 0u;
+            l2[i] = leave ? c2[(size_t)(y - lo - 1) * W] : 0u;
+            f[i] = row ? gray_at<C>(s.img + (size_t)y * W * C, x) : 0u;
         }
-        const uint32_t f = gray_at<C>(s.img + (size_t)y * W * C, x);
-        const int ny = min(y + hi, H - 1) - max(y - lo, 0) + 1;
-        const uint32_t n = (uint32_t)__mul24(nx, ny);
-        const int y0 = y & ~(kRowsPerStep - 1);
-        const bool full = block_inside && y0 - lo >= 0 && y0 + kRowsPerStep - 1 + hi <= H - 1;
-        float sq;
-        bool dark;
-        if (RULE == BZ_SAUVOLA)
-            dark = full ? dark_sauvola_row(s.dec, f, S1, S2, q_full, sq) : dark_sauvola(s.dec, f, S1, S2, n, sq);
-        else
-            dark = dark_niblack(s.dec, f, S1, S2, full ? n_full : n, sq);
-        s.out[(size_t)y * W + x] = dark ? 0 : 255;
+#pragma unroll
+        for (int i = 0; i < kColGroup; ++i) {
+            const int y = yg + i;
+            if (y >= Yend) break;
+            S1 += e1[i] - l1[i];
+            S2 += e2[i] - l2[i];
+            const int ny = min(y + hi, H - 1) - max(y - lo, 0) + 1;
+            const uint32_t n = (uint32_t)__mul24(nx, ny);
+            const int y0 = y & ~(kRowsPerStep - 1);
+            const bool full = block_inside && y0 - lo >= 0 && y0 + kRowsPerStep - 1 + hi <= H - 1;
+            float sq;
+            bool dark;
+            if (RULE == BZ_SAUVOLA)
+                dark = full ? dark_sauvola_row(s.dec, f[i], S1, S2, q_full, sq)
+                            : dark_sauvola(s.dec, f[i], S1, S2, n, sq);
+            else
+                dark = dark_niblack(s.dec, f[i], S1, S2, full ? n_full : n, sq);
+            s.out[(size_t)y * W + x] = dark ? 0 : 255;
+        }
     }
 }
 
