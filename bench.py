@@ -10,7 +10,8 @@ Prints ONE JSON line (rank 0):
   value      Gpixel/s over the timed steps (pixels binarized / time)
   roofline   achieved algorithmic HBM GB/s of the dominant kernel (Sauvola,
              gray, 256-column tiles: 2 bytes per pixel) from HIP events
-             around each of its launches, against the 8 TB/s MI355X peak
+             around each window's run of back-to-back launches, against the
+             8 TB/s MI355X peak
   cpu_baseline  the CPU oracle timed on this host on a bounded pixel sample
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -452,30 +453,33 @@ def main() -> int:
             launch(c)
     torch.cuda.synchronize()
 
-    # timed region: K steps, an event between consecutive launches
-    nl = args.steps * len(CASES)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nl + 1)]
+    # timed region: K steps, grouped by case.  The K launches of one case run
+    # back to back (each on the next buffer pair of the pool), bracketed by
+    # one pair of HIP events on the launch stream: no event marker sits
+    # between two launches of the timed work.  The five cases follow each
+    # other on the same stream, so the first start and the last end bracket
+    # all K steps.
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in CASES]
     torch.cuda.synchronize()
-    ev[0].record(stream)
     t_wall = time.perf_counter()
-    for s in range(args.steps):
-        for i, c in enumerate(CASES):
+    for i, c in enumerate(CASES):
+        ev[i][0].record(stream)
+        for _ in range(args.steps):
             launch(c)
-            ev[s * len(CASES) + i + 1].record(stream)
+        ev[i][1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    total_ms = ev[0].elapsed_time(ev[nl])
-    per = np.array([ev[j].elapsed_time(ev[j + 1]) for j in range(nl)]).reshape(args.steps, len(CASES))
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
     cases = []
     for i, (rule, win, k) in enumerate(CASES):
-        ms = float(np.mean(per[:, i]))
+        ms = case_ms[i]
         cases.append({"rule": RULE_NAME[rule], "win": win, "k": k, "ms": ms,
                       "gpix_s": px / (ms * 1e-3) / 1e9,
                       "hbm_frac": 2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS})
     # dominant kernel: the Sauvola gray launches (4 of the 5 per step)
-    sauv = per[:, [i for i, c in enumerate(CASES) if c[0] == 0]]
-    avg_ms = float(np.mean(sauv))
+    avg_ms = float(np.mean([case_ms[i] for i, c in enumerate(CASES) if c[0] == 0]))
     achieved = 2 * px / (avg_ms * 1e-3) / 1e9
 
     # achievable copy bandwidth over the same pool (plain copy kernel)
