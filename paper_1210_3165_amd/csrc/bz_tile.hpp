@@ -305,6 +305,20 @@ __device__ __forceinline__ bool dark_niblack(const PageArgs &a, uint32_t f, uint
 
 // ---------------------------------------------------------------- output
 
+// Output bytes are written once and never read back by the kernel: their
+// stores carry the non-temporal hint, so the caches treat them as streaming
+// data rather than keeping them resident next to the input rows that
+// neighbouring tiles read again.
+__device__ __forceinline__ void store_nt8(uint8_t *p, uint32_t lo, uint32_t hi) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = {lo, hi};
+    __builtin_nontemporal_store(v, (u32x2 *)p);
+}
+
+__device__ __forceinline__ void store_nt4(uint8_t *p, uint32_t w) {
+    __builtin_nontemporal_store(w, (uint32_t *)p);
+}
+
 // Store OPT output bytes (packed little-endian in w) at columns [xs, xs+OPT)
 // of an output row, skipping columns >= W.
 template <int OPT>
@@ -314,14 +328,14 @@ __device__ __forceinline__ void store_row(uint8_t *rowp, int xs, int W, const ui
         const uintptr_t ad = (uintptr_t)p;
         if ((ad & (OPT - 1)) == 0) {
             if (OPT == 8)
-                *(uint2 *)p = make_uint2(w[0], w[OPT / 4 - 1]);
+                store_nt8(p, w[0], w[OPT / 4 - 1]);
             else
-                *(uint32_t *)p = w[0];
+                store_nt4(p, w[0]);
             return;
         }
         if ((ad & 3) == 0) {
 #pragma unroll
-            for (int i = 0; i < OPT / 4; ++i) ((uint32_t *)p)[i] = w[i];
+            for (int i = 0; i < OPT / 4; ++i) store_nt4(p + 4 * i, w[i]);
             return;
         }
     }
@@ -635,9 +649,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 if (xs < a.W) {
                     uint8_t *p = a.out + (size_t)y * a.W + xs;
                     if (OPT == 8)
-                        *(uint2 *)p = make_uint2(ow[0], ow[OPT / 4 - 1]);
+                        store_nt8(p, ow[0], ow[OPT / 4 - 1]);
                     else
-                        *(uint32_t *)p = ow[0];
+                        store_nt4(p, ow[0]);
                 }
             } else {
                 store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
