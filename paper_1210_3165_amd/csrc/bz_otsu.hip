@@ -16,7 +16,8 @@
 //                fp64, and the first split of largest variance.  It stores the
 //                histogram, k* and T = k* + 1 in the workspace.
 //   otsu_apply   out = 0 where f < T, 255 elsewhere (Eq. 2), 16 pixels per
-//                lane per step, again from 16-byte loads and stores.
+//                lane per step, again from 16-byte loads and stores (the
+//                stores non-temporal: the output is not read back).
 //
 // The kernel boundaries order the three steps; every call rewrites every
 // workspace word it reads, so the workspace needs no initialisation.  The
@@ -224,6 +225,8 @@ __global__ __launch_bounds__(kHistThreads) void otsu_hist(const uint8_t *__restr
     }
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <int C, bool ALIGNED>
 __global__ __launch_bounds__(kApplyThreads) void otsu_apply(const uint8_t *__restrict__ img,
                                                             uint8_t *__restrict__ out, long npx,
@@ -240,7 +243,9 @@ __global__ __launch_bounds__(kApplyThreads) void otsu_apply(const uint8_t *__res
 #pragma unroll
             for (int p = 0; p < kPx; ++p)
                 if (level<C>(w, p) >= T) o[p >> 2] |= 0xffu << (8 * (p & 3));
-            *reinterpret_cast<uint4 *>(out + j * kPx) = make_uint4(o[0], o[1], o[2], o[3]);
+            // written once, never read back here: non-temporal (streaming) store
+            const u32x4 v = {o[0], o[1], o[2], o[3]};
+            __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(out + j * kPx));
         }
         if (blockIdx.x == 0)
             for (long i = nchunks * kPx + tid; i < npx; i += kApplyThreads)
