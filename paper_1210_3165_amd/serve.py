@@ -1,7 +1,9 @@
 """Serving loop with continuous batching for the binarizer.
 
-Requests (pages already resident in device memory) arrive over time.  The
-server:
+Requests (pages already resident in device memory) arrive over time; a
+request whose page is still being written on some stream carries the event
+recorded after that write (``Request.ready``), and its batch waits for it on
+the GPU.  The server:
 
 * admits them in arrival order while the HBM footprint of everything
   admitted and not yet finished stays within a budget (footprint of a page =
@@ -46,6 +48,7 @@ class Request:
     R: float = 128.0
     rule: int = 0
     img: object = None        # device tensor (GPU executors)
+    ready: object = None      # optional event recorded after img was written
     out: object = None        # filled by the executor
     admitted: float = math.nan
     dispatched: float = math.nan
@@ -306,11 +309,17 @@ class _GpuBase:
         self.t0_event.synchronize()
         self.t0 = clock.now()
 
-    def _begin(self, slot):
-        """Order the slot's stream after the current stream, where callers
-        usually produce the request tensors (e.g. a non-blocking upload), so
-        no kernel of the slot reads a page before it is written."""
-        self.streams[slot].wait_stream(self.torch.cuda.current_stream(self.device))
+    def _begin(self, slot, batch):
+        """Order the slot's stream after the events of the batch's requests
+        that carry one (``Request.ready``, recorded by whatever produced the
+        page, e.g. after a non-blocking upload), so no kernel of the slot
+        reads a page before it is written.  A request without an event must
+        be complete when it is submitted.  Only those events are waited on:
+        waiting on the producer's whole stream instead serialised the slots."""
+        st = self.streams[slot]
+        for r in batch:
+            if r.ready is not None:
+                st.wait_event(r.ready)
 
     def _outs(self, slot, batch):
         bufs = []
@@ -344,21 +353,25 @@ class _GpuBase:
 class GpuBatchExecutor(_GpuBase):
     """One persistent launch per micro-batch; each slot owns a stream and a
     batch object, so batches of different slots run concurrently.  A
-    micro-batch of a single page goes through the plain single-page launch,
-    which skips the batch's table copy and counter reset."""
+    micro-batch of fewer than ``min_persistent`` pages is launched page by
+    page on the slot's stream instead, which skips the batch's table copy and
+    counter reset (the persistent launch pays off once it spreads many
+    pages' tiles over the CUs)."""
 
-    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None):
+    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None,
+                 min_persistent: int = 4):
         super().__init__(slots, device)
         from . import Batch
         self.batches = [Batch(max_pages, lds_cap=lds_cap, device=self.device) for _ in range(slots)]
+        self.min_persistent = int(min_persistent)
 
     def submit(self, slot, batch, now):
-        self._begin(slot)
+        self._begin(slot, batch)
         self._outs(slot, batch)
-        if len(batch) == 1:
+        if len(batch) < self.min_persistent:
             from . import binarize
-            r = batch[0]
-            binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
+            for r in batch:
+                binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
         else:
             jobs = [(r.img, r.out, r.win, r.k, r.R, r.rule) for r in batch]
             self.batches[slot].run(jobs, use_graph=False, stream=self.streams[slot])
@@ -375,7 +388,7 @@ class GpuSingleExecutor(_GpuBase):
 
     def submit(self, slot, batch, now):
         from . import binarize
-        self._begin(slot)
+        self._begin(slot, batch)
         self._outs(slot, batch)
         for r in batch:
             binarize(r.img, r.win, r.k, r.R, r.rule, out=r.out, stream=self.streams[slot])
@@ -392,15 +405,16 @@ class GpuHostBatchExecutor(GpuBatchExecutor):
     every result out (D2H) into a pinned host buffer that becomes ``r.out``.
     A request completes when its result is in host memory."""
 
-    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None):
-        super().__init__(slots, max_pages, lds_cap, device)
+    def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None,
+                 min_persistent: int = 4):
+        super().__init__(slots, max_pages, lds_cap, device, min_persistent)
         self.host_pool = _PinnedPool()
         self.host_bufs = {}
 
     def submit(self, slot, batch, now):
         torch = self.torch
         st = self.streams[slot]
-        self._begin(slot)
+        self._begin(slot, batch)
         dev_bufs, host_bufs, jobs = [], [], []
         with torch.cuda.stream(st):
             for r in batch:
@@ -412,10 +426,10 @@ class GpuHostBatchExecutor(GpuBatchExecutor):
                 din = bi[:n_in].view(shape)
                 din.copy_(r.img, non_blocking=True)
                 jobs.append((din, bo[:r.pixels].view(r.H, r.W), r))
-            if len(jobs) == 1:
+            if len(jobs) < self.min_persistent:
                 from . import binarize
-                din, dout, r = jobs[0]
-                binarize(din, r.win, r.k, r.R, r.rule, out=dout, stream=st)
+                for din, dout, r in jobs:
+                    binarize(din, r.win, r.k, r.R, r.rule, out=dout, stream=st)
             else:
                 self.batches[slot].run([(din, dout, r.win, r.k, r.R, r.rule) for din, dout, r in jobs],
                                        use_graph=False, stream=st)

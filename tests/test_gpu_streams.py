@@ -2,7 +2,7 @@
 bytes as on the current stream; buffers the binding allocates for the call
 stay reserved until the side stream is done with them; Otsu's T and k* read
 after a side-stream run see that run; and the serving loop orders its slot
-streams after the stream that uploaded the pages.
+streams after each request's readiness event (recorded after its upload).
 
 A bounded spin kernel (torch.cuda._sleep) queued ahead of the side-stream
 work keeps that work waiting while the current stream runs, so each of the
@@ -121,10 +121,13 @@ def test_served_pages_wait_for_their_upload(bz):
     clock = WallClock()
     ex.start(clock)
     # uploads queued behind a spin on the current stream: still pending when
-    # the server dispatches
+    # the server dispatches; each request carries the event recorded after
+    # its upload
     spin(torch.cuda.current_stream())
-    for h, d in zip(host, dev):
+    for h, d, r in zip(host, dev, rs):
         d.copy_(h, non_blocking=True)
+        r.ready = torch.cuda.Event()
+        r.ready.record()
     outs = {}
 
     def keep(r):

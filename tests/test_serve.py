@@ -81,7 +81,7 @@ def test_gpu_served_mix_equals_pages_alone():
         r.img = pagegen.canvas_view(canv, H, W, C, rng)
         rs.append(r)
     assert len(rs) > 40
-    ex = GpuBatchExecutor(slots=2, max_pages=16)
+    ex = GpuBatchExecutor(slots=2, max_pages=16, min_persistent=2)  # every mix through the batch kernel
     clock = WallClock()
     ex.start(clock)
     outs = {}
@@ -120,7 +120,7 @@ def test_gpu_host_payloads_equal_pages_alone():
         assert r.img.is_pinned()
         rs.append(r)
     assert len(rs) > 30
-    ex = GpuHostBatchExecutor(slots=3, max_pages=8)
+    ex = GpuHostBatchExecutor(slots=3, max_pages=8, min_persistent=2)
     clock = WallClock()
     ex.start(clock)
     outs = {}
