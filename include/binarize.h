@@ -148,7 +148,7 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
  *
  * binarize_batch_create -- allocate a batch object for up to max_pages pages:
  *   a device page table, a pinned host staging copy of it, a work counter,
- *   a capture stream and an event.  lds_cap_bytes bounds the LDS of one
+ *   a capture stream, an event and host scratch for checking the pages.  lds_cap_bytes bounds the LDS of one
  *   workgroup (0: 80 KiB, i.e. 2 workgroups per CU); pages whose window
  *   needs more fail with BZ_ERR_TILE.  The only entry points that allocate.
  * binarize_batch_run -- plan the pages (host, into the pinned table), then

@@ -16,7 +16,6 @@
 #include <cstring>
 #include <new>
 #include <utility>
-#include <vector>
 
 #include "binarize.h"
 #include "bz_common.hpp"
@@ -119,6 +118,7 @@ struct binarize_batch {
     hipEvent_t done;     // completion of the last run (guards the pinned table)
     bool pending;
     int last_items;
+    std::pair<uintptr_t, uintptr_t> *ranges;  // host scratch, max_pages output ranges
 };
 
 namespace {
@@ -140,25 +140,24 @@ int check_page(const bz_page &p) {
 
 // The pages of a batch run concurrently, so no output may overlap another
 // page's output or any page's input (inputs may overlap each other: they
-// are only read).  Sorting the output ranges makes this O(n log n).
-int check_cross_alias(const bz_page *pages, int n) {
-    std::vector<std::pair<uintptr_t, uintptr_t>> outs;  // [begin, end)
-    outs.reserve((size_t)n);
+// are only read).  Sorting the output ranges (in `outs`, room for n) makes
+// this O(n log n).
+int check_cross_alias(const bz_page *pages, int n, std::pair<uintptr_t, uintptr_t> *outs) {
     for (int i = 0; i < n; ++i) {
         const uintptr_t o = (uintptr_t)pages[i].out;
-        outs.emplace_back(o, o + (size_t)pages[i].H * pages[i].W_img);
+        outs[i] = {o, o + (size_t)pages[i].H * pages[i].W_img};  // [begin, end)
     }
-    std::sort(outs.begin(), outs.end());
-    for (size_t i = 1; i < outs.size(); ++i)
+    std::sort(outs, outs + n);
+    for (int i = 1; i < n; ++i)
         if (outs[i].first < outs[i - 1].second) return BZ_ERR_ALIAS;
     // disjoint and sorted: ends ascend too, so the first output ending after
     // an input's start is the only candidate for overlapping it
     for (int i = 0; i < n; ++i) {
         const uintptr_t a = (uintptr_t)pages[i].img;
         const uintptr_t b = a + (size_t)pages[i].H * pages[i].W_img * pages[i].channels;
-        auto it = std::upper_bound(outs.begin(), outs.end(), a,
-                                   [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &r) { return v < r.second; });
-        if (it != outs.end() && it->first < b) return BZ_ERR_ALIAS;
+        const auto *it = std::upper_bound(outs, outs + n, a,
+                                          [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &r) { return v < r.second; });
+        if (it != outs + n && it->first < b) return BZ_ERR_ALIAS;
     }
     return BZ_OK;
 }
@@ -182,7 +181,8 @@ int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
 
 // Fill header + pages of the table at `mem`, pages grouped by tile variant;
 // returns the total item count in *items and the kinds present in *mask.
-int plan(const bz_page *pages, int n, int lds_cap, void *mem, int *items, int *mask) {
+int plan(const bz_page *pages, int n, int lds_cap, void *mem, std::pair<uintptr_t, uintptr_t> *ranges, int *items,
+         int *mask) {
     BatchHeader *hdr = (BatchHeader *)mem;
     BatchPage *bp = (BatchPage *)(hdr + 1);
     std::memset(hdr, 0, sizeof(*hdr));
@@ -198,7 +198,7 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, int *items, int *m
         const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;  // t = m either way
         kinds[(tw == 256) * 4 + (p.channels == 3) * 2 + rule]++;
     }
-    if (int rc = check_cross_alias(pages, n)) return rc;
+    if (int rc = check_cross_alias(pages, n, ranges)) return rc;
     int start[kKinds], fill[kKinds];
     for (int q = 0, acc = 0; q < kKinds; ++q) {
         start[q] = fill[q] = acc;
@@ -322,6 +322,11 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out
         return fail(e);
     }
     std::memset(b->host_table, 0, b->table_bytes);
+    b->ranges = new (std::nothrow) std::pair<uintptr_t, uintptr_t>[(size_t)max_pages];
+    if (!b->ranges) {
+        binarize_batch_destroy(b);
+        return BZ_ERR_HIP;
+    }
     *out = b;
     return BZ_OK;
 }
@@ -337,7 +342,7 @@ int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages, int
         b->pending = false;
     }
     int items = 0, mask = 0;
-    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, &items, &mask);
+    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->ranges, &items, &mask);
     if (rc) return rc;
     b->last_items = items;
     b->kind_mask = mask;
@@ -393,6 +398,7 @@ void binarize_batch_destroy(binarize_batch *b) {
     if (b->counter) (void)hipFree(b->counter);
     if (b->dev_table) (void)hipFree(b->dev_table);
     if (b->host_table) (void)hipHostFree(b->host_table);
+    delete[] b->ranges;
     delete b;
 }
 
