@@ -216,6 +216,32 @@ int binarize_otsu(const uint8_t *img, int H, int W_img, int channels, uint8_t *o
 size_t binarize_otsu_workspace_size(void);
 
 /*
+ * binarize_otsu_noalloc -- binarize_otsu for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same three launches and the same
+ * results, with the caller's workspace replaced by a scratch array inside
+ * the library: BZ_OTSU_WS_BYTES (528 KiB) per device, held until the process
+ * ends.  The call allocates nothing and calls no allocating routine; the
+ * scratch needs no clearing (every word a call reads, it first writes).
+ *   img, out: as binarize_otsu (out may be NULL: threshold only).
+ *   result: device, optional (NULL to skip), at least 258 u32 words, 4-byte
+ *     aligned; receives the histogram (words 0..255), T (word 256) and k*
+ *     (word 257), the words binarize_otsu leaves in its workspace.
+ * Sizes: as binarize_otsu (H * W_img * channels < 2^31, else BZ_ERR_SHAPE);
+ * the scratch is sized for the largest grid the call launches, so no image
+ * size depends on it.
+ * Concurrency: every call on one device shares that device's scratch.
+ * Calls that may overlap on one device (different streams without
+ * ordering, or several host threads) race and can return wrong results;
+ * order them.
+ * Errors: as binarize_otsu; BZ_ERR_WORKSPACE if result is misaligned,
+ * BZ_ERR_ALIAS if result overlaps img or out, BZ_ERR_HIP if the scratch's
+ * device address cannot be obtained.
+ */
+int binarize_otsu_noalloc(const uint8_t *img, int H, int W_img, int channels,
+                          uint8_t *out, uint32_t *result, void *stream);
+
+/*
  * Sampled-window Sauvola -- the paper's variant (Sec. 2, Eq. 5): mean m' and
  * deviation s' over a subset S' of O(W) window pixels on a geometric
  * structure, t' = m' [1 + k (s'/R' - 1)] with R' the dynamic range of s',

@@ -18,7 +18,7 @@ import torch
 
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats", "binarize_staged",
-    "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu",
+    "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu", "otsu_noalloc",
     "binarize_gs", "fmeasure_counts", "GS_PLUS", "GS_X", "GS_STAR",
 ]
 
@@ -335,6 +335,8 @@ def _otsu_lib() -> ctypes.CDLL:
         L.binarize_otsu.restype = i
         L.binarize_otsu_workspace_size.argtypes = []
         L.binarize_otsu_workspace_size.restype = ctypes.c_size_t
+        L.binarize_otsu_noalloc.argtypes = [vp, i, i, i, vp, vp, vp]
+        L.binarize_otsu_noalloc.restype = i
         if L.binarize_otsu_workspace_size() != 4 * OTSU_WS_WORDS:
             raise ImportError("libbinarize.so has a different Otsu workspace size; rebuild it")
         L._otsu_ready = True
@@ -405,6 +407,28 @@ def otsu(img: torch.Tensor, out: torch.Tensor | None = None,
     o = Otsu(img.device)
     out = o.run(img, out, stream=stream)
     return out, o.T
+
+
+def otsu_noalloc(img: torch.Tensor, out: torch.Tensor | None = None, result: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor | None:
+    """Otsu's threshold and decision through ``binarize_otsu_noalloc``: the
+    library's own scratch replaces the workspace, so the call allocates no
+    device memory when ``out`` (and ``result``, an int32 CUDA tensor of at
+    least 258 words receiving histogram, T and k*) are given.  Calls on one
+    device share that scratch and must be ordered."""
+    H, W, C = _check_image(img)
+    if out is not None and (out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device
+                            or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+    if result is not None and (result.dtype != torch.int32 or result.numel() < OTSU_WS_KSTAR + 1
+                               or result.device != img.device or not result.is_contiguous()):
+        raise ValueError("result must be a contiguous int32 tensor of >= 258 words on the image's device")
+    with torch.cuda.device(img.device):
+        s = ctypes.c_void_p(_stream_ptr(stream, img.device))
+        rc = _otsu_lib().binarize_otsu_noalloc(_ptr(img), H, W, C, _ptr(out), _ptr(result), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_otsu_noalloc")
+    return out
 
 
 # ---------------------------------------------------------------------------

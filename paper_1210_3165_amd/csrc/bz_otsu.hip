@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "binarize.h"
 #include "bz_common.hpp"
@@ -88,8 +89,11 @@ __device__ __forceinline__ double between_var(uint64_t n0, uint64_t s0, uint64_t
     return w0 * w1 * (d * d);
 }
 
-// Sum the rows of the histogram workgroups, then select k* and T.
-__global__ __launch_bounds__(kSelectThreads) void otsu_select(uint32_t *__restrict__ ws, int rows) {
+// Sum the rows of the histogram workgroups, then select k* and T.  `copy`
+// (optional) receives the histogram, T and k* as well, at the workspace's
+// offsets.
+__global__ __launch_bounds__(kSelectThreads) void otsu_select(uint32_t *__restrict__ ws, int rows,
+                                                              uint32_t *__restrict__ copy) {
     constexpr int kParts = kSelectThreads / 64;  // rows summed in parallel
     __shared__ uint4 part[kParts][64];
     __shared__ uint32_t sn[256];
@@ -171,6 +175,13 @@ __global__ __launch_bounds__(kSelectThreads) void otsu_select(uint32_t *__restri
     if (tid == 0) {
         ws[kWsK] = (uint32_t)si[0];
         ws[kWsT] = (uint32_t)si[0] + 1u;
+    }
+    if (copy) {
+        if (tid < 256) copy[kWsHist + tid] = h;
+        if (tid == 0) {
+            copy[kWsK] = (uint32_t)si[0];
+            copy[kWsT] = (uint32_t)si[0] + 1u;
+        }
     }
 }
 
@@ -283,14 +294,14 @@ unsigned grid_for(long units, int threads, long cap) {
 // Histogram + selection, then (if out is given) the decision.  A = img is
 // 16-byte aligned; the vector form of the decision also needs out aligned.
 template <int C, bool A>
-int launch_pair(const uint8_t *img, uint8_t *out, long npx, uint32_t *ws, int cus, bool aligned_out,
-                hipStream_t st) {
+int launch_pair(const uint8_t *img, uint8_t *out, long npx, uint32_t *ws, uint32_t *copy, int cus,
+                bool aligned_out, hipStream_t st) {
     const long hist_units = A ? npx / kPx : npx;
     const unsigned rows = grid_for(hist_units, kHistThreads, cus < kMaxRows ? cus : kMaxRows);
     hipLaunchKernelGGL((otsu_hist<C, A>), dim3(rows), dim3(kHistThreads), 0, st, img, npx, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
-    hipLaunchKernelGGL(otsu_select, dim3(1), dim3(kSelectThreads), 0, st, ws, (int)rows);
+    hipLaunchKernelGGL(otsu_select, dim3(1), dim3(kSelectThreads), 0, st, ws, (int)rows, copy);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
     if (!out) return BZ_OK;
@@ -304,6 +315,66 @@ int launch_pair(const uint8_t *img, uint8_t *out, long npx, uint32_t *ws, int cu
     return e == hipSuccess ? BZ_OK : fail(e);
 }
 
+// Validation and dispatch shared by both entry points: ws is the caller's
+// workspace or this library's scratch array, copy an optional second home
+// for the histogram, T and k*.
+int run_otsu(const uint8_t *img, int H, int W_img, int channels, uint8_t *out, uint32_t *ws,
+             uint32_t *copy, hipStream_t st) {
+    const int64_t npx = (int64_t)H * W_img;
+    const bool a_in = ((uintptr_t)img & 15) == 0;
+    const bool a_out = out && ((uintptr_t)out & 15) == 0;
+    const int cus = device_cus();
+    if (channels == 1)
+        return a_in ? launch_pair<1, true>(img, out, npx, ws, copy, cus, a_out, st)
+                    : launch_pair<1, false>(img, out, npx, ws, copy, cus, a_out, st);
+    return a_in ? launch_pair<3, true>(img, out, npx, ws, copy, cus, a_out, st)
+                : launch_pair<3, false>(img, out, npx, ws, copy, cus, a_out, st);
+}
+
+int check_image(const uint8_t *img, int H, int W_img, int channels, const uint8_t *out) {
+    if (!img) return BZ_ERR_NULL;
+    if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
+    if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
+    const int64_t npx = (int64_t)H * W_img;
+    if (npx * channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
+    if (out && overlaps(img, (size_t)(npx * channels), out, (size_t)npx)) return BZ_ERR_ALIAS;
+    return BZ_OK;
+}
+
+}  // namespace
+
+// Scratch of the allocation-free entry point: the words of one Otsu
+// workspace (per-workgroup histogram rows, histogram, T, k*).  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code this name is only a stand-in for the symbol: kernels receive the
+// device address looked up once per device below, never the name.
+static __device__ __align__(256) uint32_t scratch[BZ_OTSU_WS_BYTES / 4];
+
+namespace {
+
+std::once_flag g_scratch_once[kMaxDevices];
+uint32_t *g_scratch[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of this device's scratch (looked up on the first call
+// made while that device is current).
+int scratch_address(uint32_t **p) {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return fail(hipErrorInvalidDevice);
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *ptr = nullptr;
+        const hipError_t r = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[dev] = r;
+        g_scratch[dev] = r == hipSuccess ? static_cast<uint32_t *>(ptr) : nullptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess) return fail(g_scratch_err[dev]);
+    if (!g_scratch[dev]) return fail(hipErrorInvalidSymbol);
+    *p = g_scratch[dev];
+    return BZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -314,22 +385,27 @@ int binarize_otsu(const uint8_t *img, int H, int W_img, int channels, uint8_t *o
                   size_t ws_bytes, void *stream) {
     if (!img) return BZ_ERR_NULL;
     if (!ws || ws_bytes < BZ_OTSU_WS_BYTES || ((uintptr_t)ws & 15)) return BZ_ERR_WORKSPACE;
-    if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
-    if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
+    int rc = check_image(img, H, W_img, channels, out);
+    if (rc) return rc;
     const int64_t npx = (int64_t)H * W_img;
-    if (npx * channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
-    if (out && overlaps(img, (size_t)(npx * channels), out, (size_t)npx)) return BZ_ERR_ALIAS;
     if (overlaps(ws, BZ_OTSU_WS_BYTES, img, (size_t)(npx * channels))) return BZ_ERR_ALIAS;
     if (out && overlaps(ws, BZ_OTSU_WS_BYTES, out, (size_t)npx)) return BZ_ERR_ALIAS;
-    const bool a_in = ((uintptr_t)img & 15) == 0;
-    const bool a_out = out && ((uintptr_t)out & 15) == 0;
-    const int cus = device_cus();
-    hipStream_t st = (hipStream_t)stream;
-    if (channels == 1)
-        return a_in ? launch_pair<1, true>(img, out, npx, ws, cus, a_out, st)
-                    : launch_pair<1, false>(img, out, npx, ws, cus, a_out, st);
-    return a_in ? launch_pair<3, true>(img, out, npx, ws, cus, a_out, st)
-                : launch_pair<3, false>(img, out, npx, ws, cus, a_out, st);
+    return run_otsu(img, H, W_img, channels, out, ws, nullptr, (hipStream_t)stream);
+}
+
+int binarize_otsu_noalloc(const uint8_t *img, int H, int W_img, int channels, uint8_t *out,
+                          uint32_t *result, void *stream) {
+    int rc = check_image(img, H, W_img, channels, out);
+    if (rc) return rc;
+    if (result && ((uintptr_t)result & 3)) return BZ_ERR_WORKSPACE;
+    const int64_t npx = (int64_t)H * W_img;
+    const size_t rbytes = 4 * (BZ_OTSU_WS_KSTAR + 1);
+    if (result && overlaps(result, rbytes, img, (size_t)(npx * channels))) return BZ_ERR_ALIAS;
+    if (result && out && overlaps(result, rbytes, out, (size_t)npx)) return BZ_ERR_ALIAS;
+    uint32_t *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    return run_otsu(img, H, W_img, channels, out, ws, result, (hipStream_t)stream);
 }
 
 }  // extern "C"
