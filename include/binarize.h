@@ -30,8 +30,14 @@
  *               n S2 - S1^2 is formed exactly).
  * Threshold     rule BZ_SAUVOLA: t = m (1 + k (s / R - 1))   (Eq. 4)
  *               rule BZ_NIBLACK: t = m + k s                 (R unused)
- *               evaluated in fp32 from the exact integer sums; |t - t_exact|
- *               stays below 1e-4 gray levels.
+ *               from the exact integer sums: sqrt(n S2 - S1^2) in fp32, the
+ *               rest of the Sauvola threshold and its comparison in fp64,
+ *               the Niblack comparison in fp32.  For the accepted k and R
+ *               (see Limits) the threshold the decision uses, and the fp32
+ *               t plane of binarize_stats, stay within 1e-4 gray levels of
+ *               the exact t: at most about 4.5e-5 (Sauvola) and 2.5e-5
+ *               (Niblack) from the square root, plus 3.1e-5 of fp32
+ *               rounding in the t plane.
  * Output        out = 0 where f < t, 255 elsewhere (ties give 255, Eq. 3).
  * Pointers      img, out and every plane are DEVICE pointers owned by the
  *               caller (e.g. torch CUDA tensors).  The library never
@@ -52,7 +58,9 @@
  *               Faults inside a kernel surface at the caller's next
  *               synchronisation, as with any asynchronous HIP launch.
  * Limits        1 <= win <= 255; channels in {1, 3}; H, W_img >= 1;
- *               H * W_img * channels < 2^31; k finite; R finite and > 0.
+ *               H * W_img * channels < 2^31; -1 <= k <= 1; R finite and
+ *               > 0, and R >= 64 for BZ_SAUVOLA (outside this range the
+ *               1e-4 bound above would not hold: BZ_ERR_PARAM).
  * Threads       All entry points are re-entrant; calls that share a stream
  *               are ordered by that stream.
  */
@@ -75,10 +83,10 @@ extern "C" {
 /* Status codes. */
 #define BZ_OK 0
 #define BZ_ERR_NULL (-1)        /* a required pointer is NULL               */
-#define BZ_ERR_SHAPE (-2)       /* H or W_img < 1, or the image is too big  */
+#define BZ_ERR_SHAPE (-2)       /* H or W_img < 1, image too big, bad pitch */
 #define BZ_ERR_CHANNELS (-3)    /* channels not 1 or 3                      */
 #define BZ_ERR_WINDOW (-4)      /* win outside [1, 255]                     */
-#define BZ_ERR_PARAM (-5)       /* k not finite, or R not finite and > 0    */
+#define BZ_ERR_PARAM (-5)       /* |k| > 1, R <= 0, or Sauvola R < 64       */
 #define BZ_ERR_RULE (-6)        /* rule not BZ_SAUVOLA / BZ_NIBLACK         */
 #define BZ_ERR_ALIAS (-7)       /* out overlaps img (or a stats plane)      */
 #define BZ_ERR_HIP (-8)         /* the HIP runtime refused a call           */
@@ -96,6 +104,22 @@ int binarize(const uint8_t *img, int H, int W_img, int channels, int win,
 /* binarize_async -- as binarize, enqueued on `stream` (a hipStream_t). */
 int binarize_async(const uint8_t *img, int H, int W_img, int channels, int win,
                    float k, float R, int rule, uint8_t *out, void *stream);
+
+/*
+ * binarize_pitched -- as binarize_async for an image and an output whose rows
+ * are not contiguous: a crop or a padded-row layout inside a larger buffer
+ * (the M x N matrix of Sec. 1 as a window into that buffer).  pitch_in is
+ * the number of bytes from one input row to the next (>= W_img * channels),
+ * pitch_out the same for the output (>= W_img); 0 selects the contiguous
+ * pitch.  Only the H rows of W_img * channels (W_img) bytes are read
+ * (written): bytes between rows are never touched.  The output rows must
+ * not share a byte with the input rows (the test is exact, so interleaved
+ * rows of one buffer are accepted).  BZ_ERR_SHAPE for a pitch below the row
+ * size or negative; the other errors as binarize.
+ */
+int binarize_pitched(const uint8_t *img, int H, int W_img, int channels,
+                     int64_t pitch_in, int win, float k, float R, int rule,
+                     uint8_t *out, int64_t pitch_out, void *stream);
 
 /*
  * binarize_tuned -- as binarize_async with an explicit tile shape: tile_w
@@ -165,22 +189,36 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
  * binarize_batch_destroy -- wait for the last run, free everything.
  */
 typedef struct bz_page {
-    const uint8_t *img; /* device, H x W_img x channels                     */
-    uint8_t *out;       /* device, H x W_img                                */
+    const uint8_t *img; /* device, H rows of W_img x channels bytes          */
+    uint8_t *out;       /* device, H rows of W_img bytes                     */
     int H, W_img, channels, win;
     float k, R;
-    int rule;           /* BZ_SAUVOLA or BZ_NIBLACK                         */
-    int tile_w, tile_h; /* 0: chosen by the library (tile_h default 128)   */
+    int rule;           /* BZ_SAUVOLA or BZ_NIBLACK                          */
+    int tile_w, tile_h; /* 0: chosen by the library (tile_h default 128)    */
+    int64_t pitch_in;   /* bytes between input rows, 0: W_img * channels     */
+    int64_t pitch_out;  /* bytes between output rows, 0: W_img               */
 } bz_page;
 
-typedef struct binarize_batch binarize_batch;
+typedef struct bz_batch bz_batch; /* opaque batch object */
 
-int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out);
-int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages,
+/*
+ * binarize_batch -- the batched form in one call (Sec. 1, Eq. 1, 3, 4;
+ * Sec. 2 on every page): validates and plans `pages` and enqueues their
+ * persistent launch on `stream`, as binarize_batch_run without a graph.
+ * The library keeps two batch objects per device for these calls (created
+ * on first use, grown to the largest n_pages seen, kept until the process
+ * ends) and uses them in turn; a call waits on the host for the run before
+ * the previous one.  Errors as binarize_batch_run; BZ_ERR_NULL for a NULL
+ * pages array.
+ */
+int binarize_batch(const bz_page *pages, int n_pages, void *stream);
+
+int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out);
+int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages,
                        int use_graph, void *stream);
-int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap,
+int binarize_batch_info(const bz_batch *b, int *grid, int *lds_cap,
                         int *last_items);
-void binarize_batch_destroy(binarize_batch *b);
+void binarize_batch_destroy(bz_batch *b);
 
 /*
  * Otsu global threshold -- the paper's global baseline (Sec. 1, Eq. 2),
@@ -252,14 +290,16 @@ int binarize_otsu_noalloc(const uint8_t *img, int H, int W_img, int channels,
  *   BZ_GS_X     |dy| == |dx|       (both diagonals,        2 win - 1 px)
  *   BZ_GS_STAR  both               (                       4 win - 3 px)
  * clipped to the image; n' counts the in-image members.  Sums are exact,
- * s' = sqrt(n' S2' - S1'^2) / n', t' is evaluated as for binarize (fp32 from
- * the exact sums, |t' - t'_exact| < 1e-4).
+ * s' = sqrt(n' S2' - S1'^2) / n', t' is evaluated as for binarize (same
+ * precision and bound, |t' - t'_exact| < 1e-4, for -1 <= k <= 1 and
+ * R' >= 64).
  *
  * binarize_gs -- img, out as for binarize; Rp is R'.  s1, s2, n (u32) and
  *   t (f32) are optional H x W_img verification planes (NULL to skip).
  *   Errors: BZ_ERR_WINDOW for an even win or one outside [1, 255],
- *   BZ_ERR_PARAM for an unknown structure, k not finite or Rp not finite and
- *   > 0, otherwise as for binarize_stats.  No allocation, one launch.
+ *   BZ_ERR_PARAM for an unknown structure, |k| > 1 or not finite, or Rp
+ *   not finite or below 64, otherwise as for binarize_stats.  No
+ *   allocation, one launch.
  */
 #define BZ_GS_PLUS 0
 #define BZ_GS_X 1

@@ -18,7 +18,7 @@ import torch
 
 __all__ = [
     "SAUVOLA", "NIBLACK", "BinarizeError", "binarize", "binarize_stats", "binarize_staged",
-    "default_tile", "tile_lds", "library_path", "lib", "Batch", "Otsu", "otsu", "otsu_noalloc",
+    "default_tile", "tile_lds", "library_path", "lib", "Batch", "batch", "Otsu", "otsu", "otsu_noalloc",
     "binarize_gs", "fmeasure_counts", "GS_PLUS", "GS_X", "GS_STAR",
 ]
 
@@ -62,11 +62,12 @@ def lib() -> ctypes.CDLL:
     L.binarize_default_tile.argtypes = [i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
     L.binarize_tile_lds.argtypes = [i, i]
     L.binarize_staged.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, ctypes.c_size_t, vp]
+    L.binarize_pitched.argtypes = [vp, i, i, i, ctypes.c_int64, i, f, f, i, vp, ctypes.c_int64, vp]
     L.binarize_staged_workspace_size.argtypes = [i, i]
     L.binarize_staged_workspace_size.restype = ctypes.c_size_t
     for name in ("binarize", "binarize_async", "binarize_tuned", "binarize_stats",
                  "binarize_default_tile", "binarize_version", "binarize_last_hip_error",
-                 "binarize_tile_lds", "binarize_staged"):
+                 "binarize_tile_lds", "binarize_staged", "binarize_pitched"):
         getattr(L, name).restype = ctypes.c_int
     L.binarize_strerror.argtypes = [i]
     L.binarize_strerror.restype = ctypes.c_char_p
@@ -99,6 +100,30 @@ def _check_image(img: torch.Tensor) -> tuple[int, int, int]:
     raise ValueError(f"img must be HxW or HxWx3, got {tuple(img.shape)}")
 
 
+def _row_view(t: torch.Tensor, what: str) -> tuple[int, int, int, int]:
+    """(H, W, C, pitch) of an HxW or HxWx3 uint8 CUDA tensor whose rows are
+    each contiguous (a crop of a larger image, or padded rows); pitch is the
+    byte distance between rows."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8:
+        raise TypeError(f"{what} must be a uint8 torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must live on a GPU (device 'cuda'); there is no CPU path")
+    if t.dim() == 2:
+        H, W, C = t.shape[0], t.shape[1], 1
+        rows_ok = W == 1 or t.stride(1) == 1
+    elif t.dim() == 3 and t.shape[2] in (1, 3):
+        H, W, C = t.shape
+        rows_ok = (W == 1 or t.stride(1) == C) and (C == 1 or t.stride(2) == 1)
+    else:
+        raise ValueError(f"{what} must be HxW or HxWx3, got {tuple(t.shape)}")
+    if not rows_ok:
+        raise ValueError(f"{what}: each row must be contiguous (W*channels bytes)")
+    pitch = t.stride(0) if H > 1 else W * C
+    if pitch < W * C:
+        raise ValueError(f"{what}: rows overlap (row stride {pitch} < {W * C})")
+    return H, W, C, pitch
+
+
 def _stream_ptr(stream, device) -> int:
     if stream is None:
         stream = torch.cuda.current_stream(device)
@@ -126,20 +151,27 @@ def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVO
     """Binarize an HxW (gray) or HxWx3 (interleaved RGB) uint8 CUDA tensor.
 
     Returns (or fills) an HxW uint8 tensor of {0, 255} on the same device,
-    enqueued on ``stream`` (default: the current stream).  ``tile`` forces
+    enqueued on ``stream`` (default: the current stream).  ``img`` and
+    ``out`` may be row-strided views (a crop, padded rows): each row must be
+    contiguous; such calls go through ``binarize_pitched``.  ``tile`` forces
     the (tile_w, tile_h) workgroup tile; the result does not depend on it.
     """
-    H, W, C = _check_image(img)
+    H, W, C, pitch_in = _row_view(img, "img")
     if out is None:
         out = torch.empty((H, W), dtype=torch.uint8, device=img.device)
         _keep_for(stream, img.device, out)
-    elif out.shape != (H, W) or out.dtype != torch.uint8 or out.device != img.device \
-            or not out.is_contiguous():
-        raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
+    elif out.dim() != 2 or tuple(out.shape) != (H, W) or out.device != img.device:
+        raise ValueError("out must be an HxW uint8 tensor on the image's device")
+    pitch_out = _row_view(out, "out")[3]
     L = lib()
     with torch.cuda.device(img.device):
         s = ctypes.c_void_p(_stream_ptr(stream, img.device))
-        if tile is None:
+        if pitch_in != W * C or pitch_out != W:
+            if tile is not None:
+                raise ValueError("tile is only supported for contiguous images")
+            rc = L.binarize_pitched(_ptr(img), H, W, C, pitch_in, int(win), float(k), float(R), _rule(rule),
+                                    _ptr(out), pitch_out, s)
+        elif tile is None:
             rc = L.binarize_async(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule),
                                   _ptr(out), s)
         else:
@@ -231,7 +263,8 @@ class _Page(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p),
                 ("H", ctypes.c_int), ("W_img", ctypes.c_int), ("channels", ctypes.c_int),
                 ("win", ctypes.c_int), ("k", ctypes.c_float), ("R", ctypes.c_float),
-                ("rule", ctypes.c_int), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int)]
+                ("rule", ctypes.c_int), ("tile_w", ctypes.c_int), ("tile_h", ctypes.c_int),
+                ("pitch_in", ctypes.c_int64), ("pitch_out", ctypes.c_int64)]
 
 
 def _batch_lib() -> ctypes.CDLL:
@@ -246,8 +279,41 @@ def _batch_lib() -> ctypes.CDLL:
         L.binarize_batch_info.restype = ctypes.c_int
         L.binarize_batch_destroy.argtypes = [ctypes.c_void_p]
         L.binarize_batch_destroy.restype = None
+        L.binarize_batch.argtypes = [ctypes.POINTER(_Page), ctypes.c_int, ctypes.c_void_p]
+        L.binarize_batch.restype = ctypes.c_int
         L._batch_ready = True
     return L
+
+
+def _page_struct(job, i: int) -> _Page:
+    """bz_page of one job (img, out, win, k, R, rule[, (tile_w, tile_h)]);
+    img and out may be row-strided views."""
+    img, out, win, k, R, rule = job[:6]
+    tile = job[6] if len(job) > 6 and job[6] is not None else (0, 0)
+    H, W, C, pin = _row_view(img, f"page {i} img")
+    if out.dim() != 2 or tuple(out.shape) != (H, W) or out.device != img.device:
+        raise ValueError(f"page {i}: out must be an HxW uint8 tensor on the image's device")
+    pout = _row_view(out, f"page {i} out")[3]
+    return _Page(img.data_ptr(), out.data_ptr(), H, W, C, int(win), float(k), float(R),
+                 _rule(rule), int(tile[0]), int(tile[1]), pin, pout)
+
+
+def batch(jobs, stream: torch.cuda.Stream | None = None) -> None:
+    """Binarize many pages in one persistent launch through the one-call
+    ``binarize_batch`` (library-managed batch objects).  ``jobs`` as for
+    ``Batch.run``; the tensors must stay alive until the stream has
+    finished the batch."""
+    if not jobs:
+        return
+    dev = jobs[0][0].device
+    arr = (_Page * len(jobs))()
+    for i, job in enumerate(jobs):
+        arr[i] = _page_struct(job, i)
+    with torch.cuda.device(dev):
+        s = ctypes.c_void_p(_stream_ptr(stream, dev))
+        rc = _batch_lib().binarize_batch(arr, len(jobs), s)
+    if rc:
+        raise BinarizeError(rc, "binarize_batch")
 
 
 class Batch:
@@ -278,14 +344,7 @@ class Batch:
         n = len(jobs)
         arr = (_Page * max(n, 1))()
         for i, job in enumerate(jobs):
-            img, out, win, k, R, rule = job[:6]
-            tile = job[6] if len(job) > 6 and job[6] is not None else (0, 0)
-            H, W, C = _check_image(img)
-            if out.shape != (H, W) or out.dtype != torch.uint8 or not out.is_contiguous() \
-                    or out.device != img.device:
-                raise ValueError(f"page {i}: out must be a contiguous HxW uint8 tensor on the image's device")
-            arr[i] = _Page(img.data_ptr(), out.data_ptr(), H, W, C, int(win), float(k), float(R),
-                           _rule(rule), int(tile[0]), int(tile[1]))
+            arr[i] = _page_struct(job, i)
         with torch.cuda.device(self.device):
             s = ctypes.c_void_p(_stream_ptr(stream, self.device))
             rc = _batch_lib().binarize_batch_run(self._h, arr, n, 1 if use_graph else 0, s)

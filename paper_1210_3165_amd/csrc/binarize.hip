@@ -9,6 +9,7 @@
 
 #include "binarize.h"
 #include "bz_common.hpp"
+#include "bz_host.hpp"
 #include "bz_tile.hpp"
 
 using namespace bz;
@@ -26,24 +27,6 @@ int hip_fail(hipError_t e) {
     return BZ_ERR_HIP;
 }
 
-bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
-    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
-    return a0 < b0 + nb && b0 < a0 + na;
-}
-
-int validate(const uint8_t *img, int H, int W, int C, int win, float k, float R, int rule,
-             const uint8_t *out) {
-    if (!img || !out) return BZ_ERR_NULL;
-    if (H < 1 || W < 1) return BZ_ERR_SHAPE;
-    if (C != 1 && C != 3) return BZ_ERR_CHANNELS;
-    if ((int64_t)H * (int64_t)W * C >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
-    if (win < 1 || win > 255) return BZ_ERR_WINDOW;
-    if (rule != BZ_SAUVOLA && rule != BZ_NIBLACK) return BZ_ERR_RULE;
-    if (!std::isfinite(k) || !std::isfinite(R) || !(R > 0.0f)) return BZ_ERR_PARAM;
-    if (overlaps(img, (size_t)H * W * C, out, (size_t)H * W)) return BZ_ERR_ALIAS;
-    return BZ_OK;
-}
-
 // Compute units of the current device (cached per device id; threads that
 // race on the first query store the same value).
 int device_cus() {
@@ -59,63 +42,7 @@ int device_cus() {
     return v;
 }
 
-void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
-    const int w = tile_fits(256, win) ? 256 : 128;
-    int per_cu = kMaxLds / tile_lds_bytes(w, win);
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 8) per_cu = 8;  // 8 x 4 waves fill a CU
-    const long target = (long)cus * per_cu;
-    const long tiles_x = (W + w - 1) / w;
-    long h = (H * tiles_x + target - 1) / target;
-    h = (h + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep;
-    const long hmin = 64;  // keep the start-up rows (win) a modest share of the tile
-    if (h < hmin) h = hmin;
-    if (h > 4096) h = 4096;
-    *tw = w;
-    *th = (int)h;
-}
-
-struct Plan {
-    int tile_w, tile_h;
-    int lds_bytes;
-    int tiles_x, tiles_y;
-};
-
-int make_plan(int H, int W, int win, int tile_w, int tile_h, Plan *p) {
-    if (tile_w != 128 && tile_w != 256) return BZ_ERR_TILE;
-    if (tile_h < kRowsPerStep || tile_h > 4096 || tile_h % kRowsPerStep) return BZ_ERR_TILE;
-    if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
-    p->lds_bytes = tile_lds_bytes(tile_w, win);
-    p->tile_w = tile_w;
-    p->tile_h = tile_h;
-    p->tiles_x = (W + tile_w - 1) / tile_w;
-    p->tiles_y = (H + tile_h - 1) / tile_h;
-    return BZ_OK;
-}
-
-void fill_args(PageArgs *a, const uint8_t *img, int H, int W, int C, int win, float k, float R,
-               uint8_t *out, const Plan &p) {
-    a->img = img;
-    a->out = out;
-    a->gray = nullptr;
-    a->s1 = a->s2 = a->n = nullptr;
-    a->t = nullptr;
-    a->H = H;
-    a->W = W;
-    a->win = win;
-    a->lo = win / 2;
-    a->hi = win - 1 - a->lo;
-    a->k = k;
-    a->c1 = (float)(1.0 - (double)k);
-    a->c2 = (float)((double)k / (double)R);
-    a->tile_h = p.tile_h;
-    a->tiles_x = p.tiles_x;
-    a->n_tiles = p.tiles_x * p.tiles_y;
-    a->rp = ring_pitch(p.tile_w, win);
-    a->depth = ring_depth(win);
-    a->row_aligned =
-        (((uintptr_t)img & 15) == 0 && ((int64_t)W * C) % 16 == 0 && ((uintptr_t)out & 7) == 0) ? 1 : 0;
-}
+Region plane(const void *p, size_t bytes) { return Region{(uintptr_t)p, 1, (int64_t)bytes, (int64_t)bytes}; }
 
 template <int TW, int C, int RULE, bool STATS>
 int launch_t(const PageArgs &a, int lds, hipStream_t st) {
@@ -152,32 +79,25 @@ int launch(const PageArgs &a, int tile_w, int C, int rule, bool stats, int lds, 
                          : launch_c<128>(a, C, rule, stats, lds, st);
 }
 
-int run(const uint8_t *img, int H, int W, int C, int win, float k, float R, int rule, uint8_t *out,
-        int tile_w, int tile_h, uint8_t *gray, uint32_t *s1, uint32_t *s2, uint32_t *n, float *t,
-        bool stats, void *stream) {
-    int rc = validate(img, H, W, C, win, k, R, rule, out);
+int run(ImageDesc d, int win, float k, float R, int rule, int tile_w, int tile_h, uint8_t *gray, uint32_t *s1,
+        uint32_t *s2, uint32_t *n, float *t, bool stats, void *stream) {
+    int rc = check_page(d, win, k, R, rule);
     if (rc) return rc;
     if (stats) {
-        const size_t npx = (size_t)H * W;
+        const size_t npx = (size_t)d.H * d.W;
         const void *planes[5] = {gray, s1, s2, n, t};
         const size_t sizes[5] = {npx, 4 * npx, 4 * npx, 4 * npx, 4 * npx};
         for (int i = 0; i < 5; ++i) {
             if (!planes[i]) continue;
-            if (overlaps(planes[i], sizes[i], img, npx * C) || overlaps(planes[i], sizes[i], out, npx))
-                return BZ_ERR_ALIAS;
+            const Region r = plane(planes[i], sizes[i]);
+            if (regions_overlap(r, input_region(d)) || regions_overlap(r, output_region(d))) return BZ_ERR_ALIAS;
             for (int j = 0; j < i; ++j)
-                if (planes[j] && overlaps(planes[i], sizes[i], planes[j], sizes[j])) return BZ_ERR_ALIAS;
+                if (planes[j] && regions_overlap(r, plane(planes[j], sizes[j]))) return BZ_ERR_ALIAS;
         }
     }
-    if (tile_w <= 0 || tile_h <= 0) pick_default_tile(H, W, win, device_cus(), &tile_w, &tile_h);
-    Plan p;
-    rc = make_plan(H, W, win, tile_w, tile_h, &p);
-    if (rc) return rc;
-    // Sauvola with k = 0 is t = m, exactly the Niblack rule with k = 0; the
-    // Niblack form decides ties in exact integers.
-    if (rule == BZ_SAUVOLA && k == 0.0f) rule = BZ_NIBLACK;
-    PageArgs a;
-    fill_args(&a, img, H, W, C, win, k, R, out, p);
+    if (tile_w <= 0 || tile_h <= 0) pick_default_tile(d.H, d.W, win, device_cus(), &tile_w, &tile_h);
+    if ((rc = check_tile(tile_w, tile_h, win))) return rc;
+    PageArgs a = page_args(d, win, k, R, rule, tile_w, tile_h);
     if (stats) {
         a.gray = gray;
         a.s1 = s1;
@@ -185,7 +105,12 @@ int run(const uint8_t *img, int H, int W, int C, int win, float k, float R, int 
         a.n = n;
         a.t = t;
     }
-    return launch(a, p.tile_w, C, rule, stats, p.lds_bytes, (hipStream_t)stream);
+    const int kernel_rule = make_decision(rule, k, R, win).rule;
+    return launch(a, tile_w, d.C, kernel_rule, stats, tile_lds_bytes(tile_w, win), (hipStream_t)stream);
+}
+
+ImageDesc contiguous(const uint8_t *img, int H, int W, int C, uint8_t *out) {
+    return ImageDesc{img, out, H, W, C, 0, 0};
 }
 
 }  // namespace
@@ -194,31 +119,39 @@ extern "C" {
 
 int binarize(const uint8_t *img, int H, int W_img, int channels, int win, float k, float R, int rule,
              uint8_t *out) {
-    return run(img, H, W_img, channels, win, k, R, rule, out, 0, 0, nullptr, nullptr, nullptr, nullptr,
-               nullptr, false, nullptr);
+    return run(contiguous(img, H, W_img, channels, out), win, k, R, rule, 0, 0, nullptr, nullptr, nullptr,
+               nullptr, nullptr, false, nullptr);
 }
 
 int binarize_async(const uint8_t *img, int H, int W_img, int channels, int win, float k, float R,
                    int rule, uint8_t *out, void *stream) {
-    return run(img, H, W_img, channels, win, k, R, rule, out, 0, 0, nullptr, nullptr, nullptr, nullptr,
-               nullptr, false, stream);
+    return run(contiguous(img, H, W_img, channels, out), win, k, R, rule, 0, 0, nullptr, nullptr, nullptr,
+               nullptr, nullptr, false, stream);
+}
+
+int binarize_pitched(const uint8_t *img, int H, int W_img, int channels, int64_t pitch_in, int win, float k,
+                     float R, int rule, uint8_t *out, int64_t pitch_out, void *stream) {
+    if (pitch_in < 0 || pitch_out < 0) return BZ_ERR_SHAPE;
+    return run(ImageDesc{img, out, H, W_img, channels, pitch_in, pitch_out}, win, k, R, rule, 0, 0, nullptr,
+               nullptr, nullptr, nullptr, nullptr, false, stream);
 }
 
 int binarize_tuned(const uint8_t *img, int H, int W_img, int channels, int win, float k, float R,
                    int rule, uint8_t *out, int tile_w, int tile_h, void *stream) {
     if (tile_w <= 0 || tile_h <= 0) return BZ_ERR_TILE;
-    return run(img, H, W_img, channels, win, k, R, rule, out, tile_w, tile_h, nullptr, nullptr, nullptr,
-               nullptr, nullptr, false, stream);
+    return run(contiguous(img, H, W_img, channels, out), win, k, R, rule, tile_w, tile_h, nullptr, nullptr,
+               nullptr, nullptr, nullptr, false, stream);
 }
 
 int binarize_stats(const uint8_t *img, int H, int W_img, int channels, int win, float k, float R,
                    int rule, uint8_t *out, uint8_t *gray, uint32_t *s1, uint32_t *s2, uint32_t *n,
                    float *t, void *stream) {
-    return run(img, H, W_img, channels, win, k, R, rule, out, 0, 0, gray, s1, s2, n, t, true, stream);
+    return run(contiguous(img, H, W_img, channels, out), win, k, R, rule, 0, 0, gray, s1, s2, n, t, true,
+               stream);
 }
 
 int binarize_tile_lds(int tile_w, int win) {
-    if (win < 1 || win > 255) return BZ_ERR_WINDOW;
+    if (check_window(win)) return BZ_ERR_WINDOW;
     if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
     return tile_lds_bytes(tile_w, win);
 }
@@ -227,7 +160,7 @@ int binarize_default_tile(int H, int W_img, int channels, int win, int *tile_w, 
     if (!tile_w || !tile_h) return BZ_ERR_NULL;
     if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
     if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
-    if (win < 1 || win > 255) return BZ_ERR_WINDOW;
+    if (check_window(win)) return BZ_ERR_WINDOW;
     pick_default_tile(H, W_img, win, device_cus(), tile_w, tile_h);
     return BZ_OK;
 }
@@ -236,10 +169,10 @@ const char *binarize_strerror(int code) {
     switch (code) {
         case BZ_OK: return "ok";
         case BZ_ERR_NULL: return "a required pointer is NULL";
-        case BZ_ERR_SHAPE: return "image shape out of range (H, W_img >= 1, H*W_img*channels < 2^31)";
+        case BZ_ERR_SHAPE: return "image shape out of range (H, W_img >= 1, H*W_img*channels < 2^31, row pitches >= row bytes)";
         case BZ_ERR_CHANNELS: return "channels must be 1 or 3";
         case BZ_ERR_WINDOW: return "window side must be in [1, 255]";
-        case BZ_ERR_PARAM: return "k must be finite and R finite and positive";
+        case BZ_ERR_PARAM: return "k must lie in [-1, 1], R must be finite and positive, and R >= 64 for Sauvola";
         case BZ_ERR_RULE: return "rule must be BZ_SAUVOLA (0) or BZ_NIBLACK (1)";
         case BZ_ERR_ALIAS: return "output overlaps the input or another output plane";
         case BZ_ERR_HIP: return "HIP runtime error (see binarize_last_hip_error)";

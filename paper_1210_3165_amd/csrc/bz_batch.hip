@@ -14,11 +14,13 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 
 #include "binarize.h"
 #include "bz_common.hpp"
+#include "bz_host.hpp"
 #include "bz_tile.hpp"
 
 using namespace bz;
@@ -100,8 +102,14 @@ int fail(hipError_t e) {
 
 }  // namespace
 
-// Opaque batch object (binarize_batch in the C ABI).
-struct binarize_batch {
+// Bytes a page's output rows span, for the batch alias check.
+struct Span {
+    uintptr_t begin, end;
+    int page;
+};
+
+// Opaque batch object (bz_batch in the C ABI).
+struct bz_batch {
     int max_pages;
     int lds_cap;
     int grid;
@@ -118,46 +126,43 @@ struct binarize_batch {
     hipEvent_t done;     // completion of the last run (guards the pinned table)
     bool pending;
     int last_items;
-    std::pair<uintptr_t, uintptr_t> *ranges;  // host scratch, max_pages output ranges
+    Span *spans;            // host scratch for the alias check: max_pages output spans
+    uintptr_t *span_max;    // and the running maximum of their ends
+    ImageDesc *descs;       // the checked pages (pitches filled in)
 };
 
 namespace {
 
-// Validation shared with the single-page path (same rules, same codes).
-int check_page(const bz_page &p) {
-    if (!p.img || !p.out) return BZ_ERR_NULL;
-    if (p.H < 1 || p.W_img < 1) return BZ_ERR_SHAPE;
-    if (p.channels != 1 && p.channels != 3) return BZ_ERR_CHANNELS;
-    if ((int64_t)p.H * p.W_img * p.channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
-    if (p.win < 1 || p.win > 255) return BZ_ERR_WINDOW;
-    if (p.rule != BZ_SAUVOLA && p.rule != BZ_NIBLACK) return BZ_ERR_RULE;
-    if (!std::isfinite(p.k) || !std::isfinite(p.R) || !(p.R > 0.0f)) return BZ_ERR_PARAM;
-    const uintptr_t i0 = (uintptr_t)p.img, o0 = (uintptr_t)p.out;
-    const size_t ni = (size_t)p.H * p.W_img * p.channels, no = (size_t)p.H * p.W_img;
-    if (o0 < i0 + ni && i0 < o0 + no) return BZ_ERR_ALIAS;
-    return BZ_OK;
+ImageDesc page_desc(const bz_page &p) {
+    return ImageDesc{p.img, p.out, p.H, p.W_img, p.channels, p.pitch_in, p.pitch_out};
 }
 
 // The pages of a batch run concurrently, so no output may overlap another
 // page's output or any page's input (inputs may overlap each other: they
-// are only read).  Sorting the output ranges (in `outs`, room for n) makes
-// this O(n log n).
-int check_cross_alias(const bz_page *pages, int n, std::pair<uintptr_t, uintptr_t> *outs) {
+// are only read).  Output spans sorted by their first byte, with the running
+// maximum of their ends, bound the candidates of each comparison; only
+// candidates whose spans intersect get the exact strided test, so disjoint
+// pages cost O(n log n).  `descs` holds the checked pages (pitches filled).
+int check_cross_alias(const ImageDesc *descs, int n, Span *spans, uintptr_t *span_max) {
     for (int i = 0; i < n; ++i) {
-        const uintptr_t o = (uintptr_t)pages[i].out;
-        outs[i] = {o, o + (size_t)pages[i].H * pages[i].W_img};  // [begin, end)
+        const Region r = output_region(descs[i]);
+        spans[i] = Span{r.base, region_end(r), i};
     }
-    std::sort(outs, outs + n);
-    for (int i = 1; i < n; ++i)
-        if (outs[i].first < outs[i - 1].second) return BZ_ERR_ALIAS;
-    // disjoint and sorted: ends ascend too, so the first output ending after
-    // an input's start is the only candidate for overlapping it
+    std::sort(spans, spans + n, [](const Span &a, const Span &b) { return a.begin < b.begin; });
+    for (int i = 0; i < n; ++i) span_max[i] = i ? std::max(span_max[i - 1], spans[i].end) : spans[i].end;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n && spans[j].begin < spans[i].end; ++j)
+            if (regions_overlap(output_region(descs[spans[i].page]), output_region(descs[spans[j].page])))
+                return BZ_ERR_ALIAS;
     for (int i = 0; i < n; ++i) {
-        const uintptr_t a = (uintptr_t)pages[i].img;
-        const uintptr_t b = a + (size_t)pages[i].H * pages[i].W_img * pages[i].channels;
-        const auto *it = std::upper_bound(outs, outs + n, a,
-                                          [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &r) { return v < r.second; });
-        if (it != outs + n && it->first < b) return BZ_ERR_ALIAS;
+        const Region in = input_region(descs[i]);
+        const uintptr_t a = in.base, b = region_end(in);
+        // outputs starting before the input ends, latest first, while some
+        // earlier output may still end after the input starts
+        int j = (int)(std::lower_bound(spans, spans + n, b, [](const Span &s, uintptr_t v) { return s.begin < v; }) -
+                      spans) - 1;
+        for (; j >= 0 && span_max[j] > a; --j)
+            if (spans[j].end > a && regions_overlap(in, output_region(descs[spans[j].page]))) return BZ_ERR_ALIAS;
     }
     return BZ_OK;
 }
@@ -181,8 +186,8 @@ int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
 
 // Fill header + pages of the table at `mem`, pages grouped by tile variant;
 // returns the total item count in *items and the kinds present in *mask.
-int plan(const bz_page *pages, int n, int lds_cap, void *mem, std::pair<uintptr_t, uintptr_t> *ranges, int *items,
-         int *mask) {
+int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, Span *spans, uintptr_t *span_max,
+         int *items, int *mask) {
     BatchHeader *hdr = (BatchHeader *)mem;
     BatchPage *bp = (BatchPage *)(hdr + 1);
     std::memset(hdr, 0, sizeof(*hdr));
@@ -190,18 +195,19 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, std::pair<uintptr_
     int kinds[kKinds] = {0};
     for (int i = 0; i < n; ++i) {
         const bz_page &p = pages[i];
-        int rc = check_page(p);
+        descs[i] = page_desc(p);
+        int rc = check_page(descs[i], p.win, p.k, p.R, p.rule);
         if (rc) return rc;
         int tw, th;
         rc = page_tile(p, lds_cap, &tw, &th);
         if (rc) return rc;
-        const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;  // t = m either way
+        const int rule = make_decision(p.rule, p.k, p.R, p.win).rule;
         kinds[(tw == 256) * 4 + (p.channels == 3) * 2 + rule]++;
     }
-    if (int rc = check_cross_alias(pages, n, ranges)) return rc;
-    int start[kKinds], fill[kKinds];
+    if (int rc = check_cross_alias(descs, n, spans, span_max)) return rc;
+    int fill[kKinds];
     for (int q = 0, acc = 0; q < kKinds; ++q) {
-        start[q] = fill[q] = acc;
+        fill[q] = acc;
         hdr->page0[q] = (uint32_t)acc;
         hdr->n_pages[q] = (uint32_t)kinds[q];
         acc += kinds[q];
@@ -214,37 +220,17 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, std::pair<uintptr_
         const bz_page &p = pages[i];
         int tw, th;
         page_tile(p, lds_cap, &tw, &th);
-        const int rule = (p.rule == BZ_SAUVOLA && p.k == 0.0f) ? BZ_NIBLACK : p.rule;
+        const int rule = make_decision(p.rule, p.k, p.R, p.win).rule;
         const int q = (tw == 256) * 4 + (p.channels == 3) * 2 + rule;
         BatchPage &e = bp[fill[q]++];
-        PageArgs &a = e.a;
         std::memset(&e, 0, sizeof(e));
-        a.img = p.img;
-        a.out = p.out;
-        a.H = p.H;
-        a.W = p.W_img;
-        a.win = p.win;
-        a.lo = p.win / 2;
-        a.hi = p.win - 1 - a.lo;
-        a.k = p.k;
-        a.c1 = (float)(1.0 - (double)p.k);
-        a.c2 = (float)((double)p.k / (double)p.R);
-        a.tile_h = th;
-        a.tiles_x = (p.W_img + tw - 1) / tw;
-        a.n_tiles = a.tiles_x * ((p.H + th - 1) / th);
-        a.rp = ring_pitch(tw, p.win);
-        a.depth = ring_depth(p.win);
-        a.row_aligned = (((uintptr_t)p.img & 15) == 0 && ((int64_t)p.W_img * p.channels) % 16 == 0 &&
-                         ((uintptr_t)p.out & 7) == 0)
-                            ? 1
-                            : 0;
+        e.a = page_args(descs[i], p.win, p.k, p.R, p.rule, tw, th);
         e.item0 = (int)per_kind[q];
-        per_kind[q] += a.n_tiles;
-        total += a.n_tiles;
+        per_kind[q] += e.a.n_tiles;
+        total += e.a.n_tiles;
         if (per_kind[q] >= (1L << 31)) return BZ_ERR_SHAPE;
         *mask |= 1 << q;
     }
-    (void)start;
     for (int q = 0; q < kKinds; ++q) hdr->n_items[q] = (uint32_t)per_kind[q];
     *items = (int)(total < (1L << 31) ? total : (1L << 31) - 1);
     return BZ_OK;
@@ -252,7 +238,7 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, std::pair<uintptr_
 
 // Enqueue table copy, counter reset and one persistent kernel per kind in
 // `mask` (kinds run one after another on the stream).
-int record(binarize_batch *b, int mask, hipStream_t st) {
+int record(bz_batch *b, int mask, hipStream_t st) {
     hipError_t e = hipMemcpyAsync(b->dev_table, b->host_table, b->table_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(bz_counter_reset, dim3(1), dim3(64), 0, st, b->counter);
@@ -271,14 +257,14 @@ int record(binarize_batch *b, int mask, hipStream_t st) {
 
 extern "C" {
 
-int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out) {
+int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
     if (!out) return BZ_ERR_NULL;
     *out = nullptr;
     if (max_pages < 1 || max_pages > (1 << 20)) return BZ_ERR_SHAPE;
     // default: two workgroups per CU with their static LDS
     if (lds_cap_bytes <= 0) lds_cap_bytes = kMaxLds / 2 - kStaticLds;
     if (lds_cap_bytes < tile_lds_bytes(128, 1) || lds_cap_bytes > kMaxLds - kStaticLds) return BZ_ERR_TILE;
-    binarize_batch *b = new (std::nothrow) binarize_batch();
+    bz_batch *b = new (std::nothrow) bz_batch();
     if (!b) return BZ_ERR_HIP;
     b->max_pages = max_pages;
     b->lds_cap = lds_cap_bytes;
@@ -322,8 +308,10 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out
         return fail(e);
     }
     std::memset(b->host_table, 0, b->table_bytes);
-    b->ranges = new (std::nothrow) std::pair<uintptr_t, uintptr_t>[(size_t)max_pages];
-    if (!b->ranges) {
+    b->spans = new (std::nothrow) Span[(size_t)max_pages];
+    b->span_max = new (std::nothrow) uintptr_t[(size_t)max_pages];
+    b->descs = new (std::nothrow) ImageDesc[(size_t)max_pages];
+    if (!b->spans || !b->span_max || !b->descs) {
         binarize_batch_destroy(b);
         return BZ_ERR_HIP;
     }
@@ -331,7 +319,7 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, binarize_batch **out
     return BZ_OK;
 }
 
-int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages, int use_graph, void *stream) {
+int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_graph, void *stream) {
     if (!b || !pages) return BZ_ERR_NULL;
     if (n_pages < 1 || n_pages > b->max_pages) return BZ_ERR_SHAPE;
     hipStream_t st = (hipStream_t)stream;
@@ -342,7 +330,7 @@ int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages, int
         b->pending = false;
     }
     int items = 0, mask = 0;
-    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->ranges, &items, &mask);
+    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->descs, b->spans, b->span_max, &items, &mask);
     if (rc) return rc;
     b->last_items = items;
     b->kind_mask = mask;
@@ -380,7 +368,7 @@ int binarize_batch_run(binarize_batch *b, const bz_page *pages, int n_pages, int
     return BZ_OK;
 }
 
-int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap, int *last_items) {
+int binarize_batch_info(const bz_batch *b, int *grid, int *lds_cap, int *last_items) {
     if (!b) return BZ_ERR_NULL;
     if (grid) *grid = b->grid;
     if (lds_cap) *lds_cap = b->lds_cap;
@@ -388,7 +376,51 @@ int binarize_batch_info(const binarize_batch *b, int *grid, int *lds_cap, int *l
     return BZ_OK;
 }
 
-void binarize_batch_destroy(binarize_batch *b) {
+}  // extern "C"
+
+namespace {
+
+// Batch objects behind the one-call binarize_batch: two per device, used in
+// turn, so a call waits on the host only for the run before the previous
+// one (whose pinned table it rewrites).  They grow to the largest call seen
+// and live until the process ends.
+struct OneCallPool {
+    std::mutex mu;
+    bz_batch *obj[2] = {nullptr, nullptr};
+    int next = 0;
+};
+OneCallPool g_pools[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+int binarize_batch(const bz_page *pages, int n_pages, void *stream) {
+    if (!pages) return BZ_ERR_NULL;
+    if (n_pages < 1 || n_pages > (1 << 20)) return BZ_ERR_SHAPE;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(e);
+    if (dev < 0 || dev >= kMaxDevices) return fail(hipErrorInvalidDevice);
+    OneCallPool &pool = g_pools[dev];
+    std::lock_guard<std::mutex> lock(pool.mu);
+    bz_batch *&b = pool.obj[pool.next];
+    if (!b || b->max_pages < n_pages) {
+        if (b) binarize_batch_destroy(b);  // waits for its last run
+        b = nullptr;
+        int cap = 64;
+        while (cap < n_pages) cap *= 2;
+        const int rc = binarize_batch_create(cap, 0, &b);
+        if (rc) {
+            b = nullptr;
+            return rc;
+        }
+    }
+    pool.next ^= 1;
+    return binarize_batch_run(b, pages, n_pages, 0, stream);
+}
+
+void binarize_batch_destroy(bz_batch *b) {
     if (!b) return;
     if (b->pending) (void)hipEventSynchronize(b->done);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -398,7 +430,9 @@ void binarize_batch_destroy(binarize_batch *b) {
     if (b->counter) (void)hipFree(b->counter);
     if (b->dev_table) (void)hipFree(b->dev_table);
     if (b->host_table) (void)hipHostFree(b->host_table);
-    delete[] b->ranges;
+    delete[] b->spans;
+    delete[] b->span_max;
+    delete[] b->descs;
     delete b;
 }
 

@@ -30,24 +30,27 @@ constexpr int kMaxLds = 160 * 1024;                      // gfx950 LDS per workg
 // One page as the tile kernel sees it.  All geometry that depends only on the
 // page and the tile shape is computed once on the host.
 struct PageArgs {
-    const uint8_t *img;  // H x W x C, row pitch W*C
-    uint8_t *out;        // H x W
-    // verification planes (only written by the stats variant; may be null)
+    const uint8_t *img;  // H rows of W * C bytes, pitch_in bytes apart
+    uint8_t *out;        // H rows of W bytes, pitch_out bytes apart
+    // verification planes (only written by the stats variant; may be null),
+    // each H x W with rows W entries apart
     uint8_t *gray;
     uint32_t *s1;
     uint32_t *s2;
     uint32_t *n;
     float *t;
+    int64_t pitch_in, pitch_out;
+    double c1, c2;     // Sauvola: t = m (c1 + c2 s), c1 = 1 - k, c2 = k / R
+    double c1n, c2n2;  // whole windows (n = win^2): c1 / n, c2 / n^2
     int H, W;
     int win, lo, hi;  // window side and its extent above/left (lo) and below/right (hi)
     float k;          // Niblack k
-    float c1, c2;     // Sauvola: c1 = 1 - k, c2 = k / R
     int tile_h;       // output rows per workgroup (multiple of kRowsPerStep)
     int tiles_x;      // tiles per image row
     int n_tiles;      // tiles_x * tiles_y
     int rp;           // LDS ring row pitch in bytes (multiple of 16)
     int depth;        // ring depth in rows
-    int row_aligned;  // img and the row pitch W*C are multiples of 16 bytes, out of 8
+    int row_aligned;  // input rows 16-byte aligned and a multiple of 16 pixels, output rows 8-byte aligned
 };
 
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }

@@ -41,6 +41,7 @@
 
 #include "binarize.h"
 #include "bz_common.hpp"
+#include "bz_host.hpp"
 #include "bz_tile.hpp"
 
 namespace {
@@ -59,7 +60,7 @@ struct GsArgs {
     int H, W, r;
     int pitch;    // LDS row pitch (bytes)
     int tiles_x, n_tiles;
-    PageArgs dec; // k, c1 = 1 - k, c2 = k / R' for the decision helpers
+    PageArgs dec; // k, c1 = 1 - k, c2 = k / R' (fp64) for the decision helpers
 };
 
 // Staged row pitch: the tile plus halo plus up to 15 columns of chunk
@@ -385,7 +386,7 @@ int binarize_gs(const uint8_t *img, int H, int W_img, int channels, int win, flo
     if (npx * channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
     if (win < 1 || win > 255 || win % 2 == 0) return BZ_ERR_WINDOW;
     if (structure != BZ_GS_PLUS && structure != BZ_GS_X && structure != BZ_GS_STAR) return BZ_ERR_PARAM;
-    if (!std::isfinite(k) || !std::isfinite(Rp) || !(Rp > 0.0f)) return BZ_ERR_PARAM;
+    if (check_params(BZ_SAUVOLA, k, Rp)) return BZ_ERR_PARAM;  // |k| <= 1, R' >= 64: the 1e-4 bound
     const void *planes[5] = {out, s1, s2, n, t};
     const size_t sizes[5] = {(size_t)npx, 4 * (size_t)npx, 4 * (size_t)npx, 4 * (size_t)npx, 4 * (size_t)npx};
     for (int i = 0; i < 5; ++i) {
@@ -407,11 +408,12 @@ int binarize_gs(const uint8_t *img, int H, int W_img, int channels, int win, flo
     g.pitch = gs_pitch(g.r);
     g.tiles_x = (W_img + kGsTW - 1) / kGsTW;
     g.n_tiles = g.tiles_x * ((H + kGsTH - 1) / kGsTH);
-    g.dec.k = k;
-    g.dec.c1 = (float)(1.0 - (double)k);
-    g.dec.c2 = (float)((double)k / (double)Rp);
     // k = 0 makes t' = m', the Niblack form with k = 0 (exact ties)
-    const int rule = k == 0.0f ? BZ_NIBLACK : BZ_SAUVOLA;
+    const Decision q = make_decision(BZ_SAUVOLA, k, Rp, win);
+    g.dec.k = q.k;
+    g.dec.c1 = q.c1;
+    g.dec.c2 = q.c2;
+    const int rule = q.rule;
     const bool stats = s1 || s2 || n || t;
     hipStream_t st = (hipStream_t)stream;
     return channels == 1 ? gs_st<1>(g, structure, rule, stats, st) : gs_st<3>(g, structure, rule, stats, st);

@@ -27,6 +27,7 @@
 
 #include "binarize.h"
 #include "bz_common.hpp"
+#include "bz_host.hpp"
 #include "bz_tile.hpp"
 
 namespace {
@@ -44,7 +45,7 @@ struct StagedArgs {
     uint32_t *r1, *r2;  // H x W row window sums of f and f^2
     int H, W, lo, hi, win;
     int segs;      // 256-column segments per row
-    PageArgs dec;  // k, c1 = 1 - k, c2 = k / R for the decision helpers
+    PageArgs dec;  // decision constants (k, c1, c2, c1n, c2n2) for the decision helpers
 };
 
 template <int C>
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kStagedThreads) void bz_colsum(const StagedArgs s) 
     const bool block_inside = XB - lo >= 0 && XB + 255 + hi <= W - 1;
     const int nx = min(x + hi, W - 1) - max(x - lo, 0) + 1;
     const uint32_t n_full = (uint32_t)__mul24(win, win);
-    const RowSauvola q_full = row_sauvola(s.dec, n_full);
+    const WholeWindow q_full = whole_window(s.dec, n_full);
     const int Yend = min(Y0 + kColTH, H);
     // Rows go in groups of kColGroup: the entering and leaving plane entries
     // and the gray levels of a whole group are loaded before any is used, so
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kStagedThreads) void bz_colsum(const StagedArgs s) 
             float sq;
             bool dark;
             if (RULE == BZ_SAUVOLA)
-                dark = full ? dark_sauvola_row(s.dec, f[i], S1, S2, q_full, sq)
+                dark = full ? dark_sauvola_full(q_full, f[i], S1, S2, sq)
                             : dark_sauvola(s.dec, f[i], S1, S2, n, sq);
             else
                 dark = dark_niblack(s.dec, f[i], S1, S2, full ? n_full : n, sq);
@@ -168,11 +169,6 @@ __global__ __launch_bounds__(kStagedThreads) void bz_colsum(const StagedArgs s) 
 int fail(hipError_t e) {
     set_last_hip_error((int)e);
     return BZ_ERR_HIP;
-}
-
-bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
-    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
-    return a0 < b0 + nb && b0 < a0 + na;
 }
 
 template <int C, int RULE>
@@ -197,19 +193,15 @@ size_t binarize_staged_workspace_size(int H, int W_img) {
 
 int binarize_staged(const uint8_t *img, int H, int W_img, int channels, int win, float k, float R, int rule,
                     uint8_t *out, uint32_t *ws, size_t ws_bytes, void *stream) {
-    if (!img || !out) return BZ_ERR_NULL;
-    if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
-    if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
+    ImageDesc d{img, out, H, W_img, channels, 0, 0};
+    int rc = check_page(d, win, k, R, rule);
+    if (rc) return rc;
     const size_t npx = (size_t)H * (size_t)W_img;
-    if ((int64_t)npx * channels >= ((int64_t)1 << 31)) return BZ_ERR_SHAPE;
-    if (win < 1 || win > 255) return BZ_ERR_WINDOW;
-    if (rule != BZ_SAUVOLA && rule != BZ_NIBLACK) return BZ_ERR_RULE;
-    if (!std::isfinite(k) || !std::isfinite(R) || !(R > 0.0f)) return BZ_ERR_PARAM;
     if (!ws || ws_bytes < 8 * npx || ((uintptr_t)ws & 3)) return BZ_ERR_WORKSPACE;
-    if (overlaps(img, npx * channels, out, npx)) return BZ_ERR_ALIAS;
-    if (overlaps(ws, 8 * npx, img, npx * channels) || overlaps(ws, 8 * npx, out, npx)) return BZ_ERR_ALIAS;
-    // Sauvola with k = 0 is t = m, the Niblack rule with k = 0 (as binarize)
-    if (rule == BZ_SAUVOLA && k == 0.0f) rule = BZ_NIBLACK;
+    const Region wr{(uintptr_t)ws, 1, (int64_t)(8 * npx), (int64_t)(8 * npx)};
+    if (regions_overlap(wr, input_region(d)) || regions_overlap(wr, output_region(d))) return BZ_ERR_ALIAS;
+    const Decision q = make_decision(rule, k, R, win);
+    rule = q.rule;
     StagedArgs s;
     s.img = img;
     s.out = out;
@@ -222,9 +214,11 @@ int binarize_staged(const uint8_t *img, int H, int W_img, int channels, int win,
     s.hi = win - 1 - s.lo;
     s.segs = (W_img + kSegW - 1) / kSegW;
     s.dec = PageArgs{};
-    s.dec.k = k;
-    s.dec.c1 = (float)(1.0 - (double)k);
-    s.dec.c2 = (float)((double)k / (double)R);
+    s.dec.k = q.k;
+    s.dec.c1 = q.c1;
+    s.dec.c2 = q.c2;
+    s.dec.c1n = q.c1n;
+    s.dec.c2n2 = q.c2n2;
     hipStream_t st = (hipStream_t)stream;
     if (channels == 1)
         return rule == BZ_SAUVOLA ? staged_launch<1, BZ_SAUVOLA>(s, st) : staged_launch<1, BZ_NIBLACK>(s, st);

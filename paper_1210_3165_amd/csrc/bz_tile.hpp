@@ -191,7 +191,7 @@ struct Stager {
                 xs = min(max(xs, 0), a.W - 16);
             }
             const int rc = min(max(row, 0), a.H - 1);
-            fetch_chunk<C, INT>(k, a.img + (size_t)rc * (size_t)a.W * C, xs, a.W, clamp);
+            fetch_chunk<C, INT>(k, a.img + (size_t)rc * (size_t)a.pitch_in, xs, a.W, clamp);
         }
     }
 
@@ -237,69 +237,77 @@ __device__ __forceinline__ uint32_t half_total(uint32_t incl) {
 //
 // Eq. 3 decides f < t.  With the exact integer window sums S1, S2 and count n,
 // m = S1 / n and s = sqrt(D) / n where D = n S2 - S1^2 is formed exactly in
-// fp64 (every term is an integer below 2^53).
+// fp64 (every term is an integer below 2^53); sqrt(D) is taken in fp32.
 //
-//   Sauvola (Eq. 4), steps whose windows are all whole (n = win^2 for the
-//   whole tile, so c1/n and c2/n^2 are computed once per tile):
-//       f < t  <=>  f < S1 (c1/n + (c2/n^2) sqrt(D)),  c1 = 1 - k, c2 = k / R
-//   Sauvola, clipped windows (n per pixel, no division):
+//   Sauvola (Eq. 4), t = m (c1 + c2 s) with c1 = 1 - k, c2 = k / R, both
+//   sides scaled by n (fp64 after the square root):
+//     steps whose windows are all whole (n = win^2, constants per page):
+//       f < t  <=>  f < S1 (c1/n + (c2/n^2) sqrt(D))
+//     clipped windows (n per pixel, no division):
 //       f < t  <=>  (n f) n < S1 (n c1 + c2 sqrt(D))
-//   Niblack:
-//       f < m + k s  <=>  n f - S1 < k sqrt(D)          (n f, S1 exact integers)
+//   Niblack, t = m + k s (fp32; n f - S1 is an exact integer below 2^24):
+//       f < t  <=>  n f - S1 < k sqrt(D)
 //
-// Niblack therefore decides ties exactly: a window of constant gray level
-// (D = 0) gives f = t and the output 255.  A Sauvola call with k = 0 is the
-// same rule (t = m) and is routed to the Niblack form by the host.
+// The only sizeable rounding is that of sqrt(D) in fp32 (relative 1.35e-7
+// at most), which moves the Sauvola threshold by at most
+// m |k| s / R * 1.35e-7 and the Niblack threshold by |k| s * 1.9e-7 with the
+// fp32 product: below 4.5e-5 and 2.5e-5 in the accepted range |k| <= 1,
+// R >= 64 (Sauvola).  Niblack decides ties exactly: a window of constant
+// gray level (D = 0) gives f = t and the output 255.  A Sauvola call with
+// k = 0 is the same rule (t = m) and is routed to the Niblack form by the
+// host.
 
-// Per-tile constants of the whole-window Sauvola form.
-struct RowSauvola {
-    double nd;
-    float c1n, c2n2;
+// Whole-window Sauvola constants of a page: n = win^2, c1 / n, c2 / n^2.
+struct WholeWindow {
+    double nd, c1n, c2n2;
 };
 
-__device__ __forceinline__ RowSauvola row_sauvola(const PageArgs &a, uint32_t n) {
-    RowSauvola q;
+__device__ __forceinline__ WholeWindow whole_window(const PageArgs &a, uint32_t n) {
+    WholeWindow q;
     q.nd = (double)n;
-    const float nf = (float)n;
-    q.c1n = a.c1 / nf;
-    q.c2n2 = a.c2 / (nf * nf);
+    q.c1n = a.c1n;
+    q.c2n2 = a.c2n2;
     return q;
 }
 
-__device__ __forceinline__ float exact_sqrt_d(double nd, uint32_t S1, uint32_t S2) {
-    const double s1d = (double)S1;
+// sqrt(D) in fp32 with D = n S2 - S1^2 exact in fp64; s1d receives S1.
+__device__ __forceinline__ float exact_sqrt_d(double nd, uint32_t S1, uint32_t S2, double &s1d) {
+    s1d = (double)S1;
     const double D = __builtin_fma(nd, (double)S2, -(s1d * s1d));
     return __builtin_amdgcn_sqrtf((float)D);
 }
 
-// t itself (fp32, verification planes only).
+// t itself, fp64 rounded to fp32 (verification planes only).
 template <int RULE>
 __device__ __forceinline__ float threshold_value(const PageArgs &a, uint32_t S1, uint32_t n, float sq) {
-    const float nf = (float)n;
-    const float m = (float)S1 / nf;
-    const float s = sq / nf;
-    return RULE == 0 ? m * __builtin_fmaf(a.c2, s, a.c1) : __builtin_fmaf(a.k, s, m);
+    const double nd = (double)n;
+    const double m = (double)S1 / nd;
+    const double s = (double)sq / nd;
+    return (float)(RULE == 0 ? m * __builtin_fma(a.c2, s, a.c1) : __builtin_fma((double)a.k, s, m));
 }
 
-// Whole-window Sauvola (per-tile constants): true if f < t (output 0).
-__device__ __forceinline__ bool dark_sauvola_row(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
-                                                 const RowSauvola &q, float &sq) {
-    sq = exact_sqrt_d(q.nd, S1, S2);
-    return (float)f < (float)S1 * __builtin_fmaf(q.c2n2, sq, q.c1n);
+// Whole-window Sauvola (per-page constants): true if f < t (output 0).
+__device__ __forceinline__ bool dark_sauvola_full(const WholeWindow &q, uint32_t f, uint32_t S1, uint32_t S2,
+                                                  float &sq) {
+    double s1d;
+    sq = exact_sqrt_d(q.nd, S1, S2, s1d);
+    return (double)f < s1d * __builtin_fma(q.c2n2, (double)sq, q.c1n);
 }
 
 // Sauvola, any n.
 __device__ __forceinline__ bool dark_sauvola(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
                                              uint32_t n, float &sq) {
-    sq = exact_sqrt_d((double)n, S1, S2);
-    const float nf = (float)n;
-    return (float)__umul24(n, f) * nf < (float)S1 * __builtin_fmaf(a.c2, sq, a.c1 * nf);
+    const double nd = (double)n;
+    double s1d;
+    sq = exact_sqrt_d(nd, S1, S2, s1d);
+    return (double)__umul24(n, f) * nd < s1d * __builtin_fma(a.c2, (double)sq, a.c1 * nd);
 }
 
 // Niblack, any n.
 __device__ __forceinline__ bool dark_niblack(const PageArgs &a, uint32_t f, uint32_t S1, uint32_t S2,
                                             uint32_t n, float &sq) {
-    sq = exact_sqrt_d((double)n, S1, S2);
+    double s1d;
+    sq = exact_sqrt_d((double)n, S1, S2, s1d);
     return (float)((int)__umul24(n, f) - (int)S1) < a.k * sq;
 }
 
@@ -499,7 +507,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const bool x_inside = XB - lo >= 0 && XB + 255 + hi <= a.W - 1;
     // steps whose windows are all whole: n = win^2, Sauvola constants per tile
     const uint32_t n_full = (uint32_t)__mul24(win, win);
-    const RowSauvola q_full = row_sauvola(a, n_full);
+    const WholeWindow q_full = whole_window(a, n_full);
 
     // The rows of the first step go in behind the start-up rows (slots the
     // start-up reads do not touch); the rows of the second step are requested.
@@ -609,7 +617,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             if (RULE == 0) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const bool dark = dark_sauvola_row(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], q_full, sqv[j]);
+                    const bool dark = dark_sauvola_full(q_full, byte_at(fw, j), b1 + E1[j], b2 + E2[j], sqv[j]);
                     ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
                 }
             } else {
@@ -647,14 +655,14 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         if (y < Yend) {
             if (INT) {  // W is a multiple of 16: the thread's outputs lie wholly inside or outside
                 if (xs < a.W) {
-                    uint8_t *p = a.out + (size_t)y * a.W + xs;
+                    uint8_t *p = a.out + (size_t)y * (size_t)a.pitch_out + xs;
                     if (OPT == 8)
                         store_nt8(p, ow[0], ow[OPT / 4 - 1]);
                     else
                         store_nt4(p, ow[0]);
                 }
             } else {
-                store_row<OPT>(a.out + (size_t)y * a.W, xs, a.W, ow);
+                store_row<OPT>(a.out + (size_t)y * (size_t)a.pitch_out, xs, a.W, ow);
             }
             if (STATS) {
 #pragma unroll

@@ -74,6 +74,79 @@ def test_invalid_arguments_are_rejected_before_launch(L, args, code):
     assert L.binarize_async(*a, None) == code
 
 
+@pytest.mark.parametrize("rule,k,R,code", [
+    (0, 1.0001, 128.0, -5),    # |k| > 1
+    (0, -1.5, 128.0, -5),
+    (1, 2.0, 128.0, -5),
+    (0, 0.5, 63.99, -5),       # Sauvola R < 64
+    (0, 0.5, 1.0, -5),
+    (1, -0.2, -1.0, -5),       # R must still be positive for Niblack
+])
+def test_parameter_range(L, rule, k, R, code):
+    """Outside |k| <= 1 (and R >= 64 for Sauvola) the 1e-4 threshold bound
+    does not hold, so the call is refused before any launch."""
+    vp = ctypes.c_void_p
+    assert L.binarize(vp(FAKE_IN), 16, 16, 1, 15, k, R, rule, vp(FAKE_OUT)) == code
+
+
+@pytest.mark.parametrize("rule,k,R", [(0, 1.0, 64.0), (0, -1.0, 64.0), (1, -1.0, 1.0), (1, 1.0, 0.5)])
+def test_parameter_range_limits_pass_validation(L, rule, k, R):
+    """The limits themselves are accepted: validation passes and the call
+    goes on to the launch (which needs a GPU, so here it may only fail in the
+    HIP runtime, never with BZ_ERR_PARAM)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("would launch on the GPU with fake pointers")
+    vp = ctypes.c_void_p
+    assert L.binarize(vp(FAKE_IN), 16, 16, 1, 15, k, R, rule, vp(FAKE_OUT)) not in (-1, -2, -3, -4, -5, -6, -7)
+
+
+def _pitched(L):
+    vp, i, f, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_int64
+    L.binarize_pitched.argtypes = [vp, i, i, i, i64, i, f, f, i, vp, i64, vp]
+    L.binarize_pitched.restype = i
+    return L.binarize_pitched
+
+
+@pytest.mark.parametrize("img,H,W,C,pin,out,pout,code", [
+    (FAKE_IN, 16, 16, 1, 15, FAKE_OUT, 0, -2),            # input pitch below the row
+    (FAKE_IN, 16, 16, 3, 47, FAKE_OUT, 0, -2),
+    (FAKE_IN, 16, 16, 1, 0, FAKE_OUT, 15, -2),            # output pitch below the row
+    (FAKE_IN, 16, 16, 1, -32, FAKE_OUT, 0, -2),           # negative pitch
+    (FAKE_IN, 16, 16, 1, 64, FAKE_IN + 8, 64, -7),        # output rows straddle input rows
+    (FAKE_IN, 16, 48, 1, 64, FAKE_IN + 40, 64, -7),       # output row i starts in input row i
+    (FAKE_IN, 16, 16, 1, 64, FAKE_IN + 64 * 15 + 4, 64, -7),  # output row 0 inside the last input row
+    (FAKE_IN, 16, 16, 1, 64, FAKE_IN - 64 * 15 + 12, 64, -7),  # last output row over input row 0
+    (None, 16, 16, 1, 64, FAKE_OUT, 64, -1),
+])
+def test_pitched_invalid_arguments(L, img, H, W, C, pin, out, pout, code):
+    fn = _pitched(L)
+    vp = ctypes.c_void_p
+    assert fn(vp(img) if img else None, H, W, C, pin, 15, 0.5, 128.0, 0, vp(out), pout, None) == code
+
+
+def test_pitched_interleaved_rows_pass_alias_check(L):
+    """Input and output rows interleaved in one buffer, never sharing a byte:
+    the exact strided test accepts them (the call proceeds to the launch)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("would launch on the GPU with fake pointers")
+    fn = _pitched(L)
+    vp = ctypes.c_void_p
+    # input rows at [64 i, 64 i + 16), output rows at [64 i + 32, 64 i + 48)
+    assert fn(vp(FAKE_IN), 16, 16, 1, 64, 15, 0.5, 128.0, 0, vp(FAKE_IN + 32), 64, None) not in (-2, -7)
+
+
+def test_batch_one_call_arguments(L):
+    import paper_1210_3165_amd as bz
+    Lb = bz._batch_lib()
+    assert Lb.binarize_batch(None, 1, None) == -1
+    arr = (bz._Page * 1)()
+    assert Lb.binarize_batch(arr, 0, None) == -2
+    arr[0] = bz._Page(FAKE_IN, FAKE_IN + 8, 16, 16, 1, 15, 0.5, 128.0, 0, 0, 0, 0, 0)
+    assert Lb.binarize_batch(arr, 1, None) in (-7, -8)  # alias, or the HIP runtime without a GPU
+
+
 def test_stats_planes_must_not_alias(L):
     vp = ctypes.c_void_p
     base = [vp(FAKE_IN), 16, 16, 1, 15, 0.5, 128.0, 0, vp(FAKE_OUT)]
@@ -159,6 +232,8 @@ def test_otsu_workspace_contract(L):
     ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 3, FAKE_OUT), -5),        # unknown structure
     ((FAKE_IN, 16, 16, 1, 15, 0.5, -1.0, 0, FAKE_OUT), -5),         # R' <= 0
     ((FAKE_IN, 16, 16, 1, 15, float("inf"), 128.0, 0, FAKE_OUT), -5),
+    ((FAKE_IN, 16, 16, 1, 15, 1.5, 128.0, 0, FAKE_OUT), -5),        # |k| > 1
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 32.0, 0, FAKE_OUT), -5),         # R' < 64
     ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 2, FAKE_IN + 10), -7),    # out inside img
 ])
 def test_gs_invalid_arguments(L, args, code):
@@ -201,6 +276,8 @@ STAGED_WS = 8 * 16 * 16
     ((FAKE_IN, 16, 16, 2, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -3),         # two channels
     ((FAKE_IN, 16, 16, 1, 256, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -4),        # window too wide
     ((FAKE_IN, 16, 16, 1, 15, float("nan"), 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -5),
+    ((FAKE_IN, 16, 16, 1, 15, -1.25, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -5),       # |k| > 1
+    ((FAKE_IN, 16, 16, 1, 15, 0.5, 16.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS), -5),          # Sauvola R < 64
     ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 2, FAKE_OUT, FAKE_WS, STAGED_WS), -6),         # unknown rule
     ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, None, STAGED_WS), -10),           # no workspace
     ((FAKE_IN, 16, 16, 1, 15, 0.5, 128.0, 0, FAKE_OUT, FAKE_WS, STAGED_WS - 1), -10),    # too small

@@ -302,7 +302,7 @@ def test_aligned_pages_outside_chunks(bz, oracle_mod, H, W, win):
             assert np.array_equal(out.cpu().numpy(), aligned), (H, W, C, win, rule)
 
 
-# ------------------------------------------------------------ full size, sampled
+# ------------------------------------------------------------ full size
 
 def sample_points(H, W, win, n, seed):
     rng = np.random.default_rng(seed)
@@ -317,39 +317,51 @@ def sample_points(H, W, win, n, seed):
     return np.array(ys, np.int32), np.array(xs, np.int32)
 
 
+@pytest.fixture(scope="module")
+def page4096():
+    import pagegen
+    return pagegen.config1()[0].img
+
+
 @pytest.mark.parametrize("rule,win,k", [(0, 15, 0.5), (0, 31, 0.5), (0, 61, 0.5), (0, 101, 0.5),
                                         (1, 31, -0.2)])
-def test_full_size_4096_sampled(bz, oracle_mod, rule, win, k):
-    """The full 4096 x 4096 page with the default launch configuration (the
-    one the benchmark times), checked against the oracle at sampled pixels."""
-    import pagegen
-    from oracle.compare import as_u32, compare_out
-    img = pagegen.config1()[0].img
+def test_full_size_4096_full_page(bz, oracle_mod, page4096, rule, win, k):
+    """The whole 4096 x 4096 page in the default launch configuration (the
+    one the benchmark times) against the oracle at every pixel: gray, S1,
+    S2 and n bit-identical, t within 1e-4, the output band-aware; the product
+    entry point gives the stats run's bytes; corners, borders and tile seams
+    are asserted again on their own."""
+    from oracle.compare import as_u32, compare_out, compare_stats
+    img = page4096
     k = f32(k)
+    print(f"4096 full page: rule {rule} win {win}", flush=True)
     timg = torch.from_numpy(img).cuda()
     out = bz.binarize(timg, win, k, 128.0, rule).cpu().numpy()
     st = {n: v.cpu().numpy() for n, v in bz.binarize_stats(timg, win, k, 128.0, rule).items()}
-    ys, xs = sample_points(4096, 4096, win, 3000, seed=win)
-    ref = oracle_mod.binarize_points(img, win, k, 128.0, rule, ys, xs)
-    assert np.array_equal(st["gray"][ys, xs], ref.gray)
-    assert np.array_equal(as_u32(st["s1"][ys, xs]), ref.s1)
-    assert np.array_equal(as_u32(st["s2"][ys, xs]), ref.s2)
-    assert np.array_equal(as_u32(st["n"][ys, xs]), ref.n)
-    assert np.max(np.abs(st["t"][ys, xs] - ref.t)) <= 1e-4
-    assert compare_out(out[ys, xs], ref.out, ref.gray, ref.t)["ok"]
+    ref = oracle_mod.binarize(img, win, k, 128.0, rule)
+    rep = compare_stats(st, ref)
+    print("4096", rule, win, rep, flush=True)
+    assert rep["ok"], rep
+    assert compare_out(out, ref.out, ref.gray, ref.t)["ok"]
     assert np.array_equal(out, st["out"])
-    assert np.all((out == 0) | (out == 255))
+    ys, xs = sample_points(4096, 4096, win, 0, seed=win)
+    assert np.array_equal(as_u32(st["s1"][ys, xs]), ref.s1[ys, xs])
+    assert np.array_equal(as_u32(st["n"][ys, xs]), ref.n[ys, xs])
+    assert compare_out(out[ys, xs], ref.out[ys, xs], ref.gray[ys, xs], ref.t[ys, xs])["ok"]
 
 
-def test_rgb_a4_page_sampled(bz, oracle_mod):
+def test_rgb_a4_page_full(bz, oracle_mod):
+    """One A4 RGB page of the batch workload (3508 x 2480, win 31, k 0.34),
+    every pixel against the oracle."""
     import pagegen
     from oracle.compare import compare_out
     job = pagegen.config2(n_pages=1)[0]
     k = f32(job.k)
     out = bz.binarize(torch.from_numpy(job.img).cuda(), job.win, k, 128.0, 0).cpu().numpy()
-    ys, xs = sample_points(job.H, job.W, job.win, 3000, seed=7)
-    ref = oracle_mod.binarize_points(job.img, job.win, k, 128.0, 0, ys, xs)
-    assert compare_out(out[ys, xs], ref.out, ref.gray, ref.t)["ok"]
+    ref = oracle_mod.binarize(job.img, job.win, k, 128.0, 0)
+    rep = compare_out(out, ref.out, ref.gray, ref.t)
+    print("a4 rgb", rep, flush=True)
+    assert rep["ok"], rep
 
 
 # ------------------------------------------------------------ errors
