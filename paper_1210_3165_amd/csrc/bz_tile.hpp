@@ -54,29 +54,28 @@ __device__ __forceinline__ uint32_t byte_at(const uint32_t (&w)[N], int i) {
 
 // Difference and sum of byte B of two words, each one VALU instruction with
 // byte-select operands (plain arithmetic instructions, no memory access).
-template <int B>
-__device__ __forceinline__ int byte_sub(uint32_t x, uint32_t y) {
-    int d;
-    if (B == 0)
-        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0"
-            : "=v"(d) : "v"(x), "v"(y));
-    else
-        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1"
-            : "=v"(d) : "v"(x), "v"(y));
-    return d;
-}
-
-template <int B>
-__device__ __forceinline__ int byte_add(uint32_t x, uint32_t y) {
-    int d;
-    if (B == 0)
-        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0"
-            : "=v"(d) : "v"(x), "v"(y));
-    else
-        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1"
-            : "=v"(d) : "v"(x), "v"(y));
-    return d;
-}
+#define BZ_SDWA_BYTE_OP(NAME, OP)                                                                          \
+    template <int B>                                                                                       \
+    __device__ __forceinline__ int NAME(uint32_t x, uint32_t y) {                                          \
+        static_assert(B >= 0 && B <= 3, "byte index");                                                     \
+        int d;                                                                                             \
+        if (B == 0)                                                                                        \
+            asm(OP " %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0 src1_sel:BYTE_0"       \
+                : "=v"(d) : "v"(x), "v"(y));                                                               \
+        else if (B == 1)                                                                                   \
+            asm(OP " %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 src1_sel:BYTE_1"       \
+                : "=v"(d) : "v"(x), "v"(y));                                                               \
+        else if (B == 2)                                                                                   \
+            asm(OP " %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2 src1_sel:BYTE_2"       \
+                : "=v"(d) : "v"(x), "v"(y));                                                               \
+        else                                                                                               \
+            asm(OP " %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_3 src1_sel:BYTE_3"       \
+                : "=v"(d) : "v"(x), "v"(y));                                                               \
+        return d;                                                                                          \
+    }
+BZ_SDWA_BYTE_OP(byte_sub, "v_sub_u32_sdwa")
+BZ_SDWA_BYTE_OP(byte_add, "v_add_u32_sdwa")
+#undef BZ_SDWA_BYTE_OP
 
 // ---------------------------------------------------------------- staging
 //
