@@ -204,12 +204,16 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
     return res
 
 
-def run_serve_workload(rates, duration: float, slots: int, max_pages: int, payload: str = "device") -> dict:
+def run_serve_workload(rates, duration: float, slots: int, max_pages: int, payload: str = "device",
+                       sizes: str = "config4", warm: bool = True) -> dict:
     """Poisson request streams served on the same inputs in several modes:
     device-resident payloads with continuous batching (persistent batched
     launches on `slots` streams) and in the plain form (one launch per
     request); host-origin payloads (pinned host in and out, copies on the
-    slots' streams) batched and one request per batch."""
+    slots' streams) batched and one request per batch.  sizes: "config4"
+    (the served mix: 0.1-16 Mpx, gray or RGB, odd win 15-151) or "page4096"
+    (every request a 4096^2 gray page, Sauvola win 31: the size at which a
+    few thousand requests per second approach the GPU's capacity)."""
     import torch
 
     import pagegen
@@ -224,10 +228,21 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int, paylo
     modes = {"device": ["batched", "single"], "host": ["host-batched", "host-single"],
              "both": ["batched", "single", "host-batched", "host-single"]}[payload]
 
+    def stream(rate, seed):
+        if sizes == "config4":
+            return pagegen.config4_stream(rate, duration, seed)
+        rng = np.random.default_rng(seed)
+        t, out = 0.0, []
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t >= duration or len(out) >= 10_000:
+                return out
+            out.append((t, 4096, 4096, 1, 31, 0.5))
+
     def requests(rate, seed, where):
         rng = np.random.default_rng(seed)
         out = []
-        for i, (t, H, W, C, win, k) in enumerate(pagegen.config4_stream(rate, duration, seed)):
+        for i, (t, H, W, C, win, k) in enumerate(stream(rate, seed)):
             r = Request(i, t, H, W, C, win, k)
             r.img = pagegen.canvas_view(canv[where], H, W, C, rng)
             out.append(r)
@@ -235,11 +250,12 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int, paylo
 
     def serve(mode, reqs):
         if mode == "batched":
-            ex, mp = GpuBatchExecutor(slots, max_pages), max_pages
+            ex, mp = GpuBatchExecutor(slots, max_pages, pool_cap=budget), max_pages
         elif mode == "single":
-            ex, mp = GpuSingleExecutor(slots), 1
+            ex, mp = GpuSingleExecutor(slots, pool_cap=budget), 1
         else:
-            ex, mp = GpuHostBatchExecutor(slots, max_pages), (max_pages if mode == "host-batched" else 1)
+            ex, mp = (GpuHostBatchExecutor(slots, max_pages, pool_cap=budget),
+                      (max_pages if mode == "host-batched" else 1))
         clock = WallClock()
         ex.start(clock)
         st = Server(ex, budget, max_batch_pages=mp).run(reqs, clock)
@@ -250,15 +266,114 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int, paylo
         s["payload_GBps"] = sum(r.footprint for r in st.completed) / span / 1e9 if span > 0 else 0.0
         return s
 
-    for mode in modes:  # warm-up (kernels loaded, pools filled)
-        serve(mode, requests(1000.0, 1, "host" if mode.startswith("host") else "device")[:100])
-    res = {"workload": "serve", "duration_s": duration, "slots": slots, "max_batch_pages": max_pages,
-           "hbm_budget_GB": budget / 1e9, "payload": payload, "runs": []}
+    if warm:
+        for mode in modes:  # warm-up (kernels loaded, pools filled)
+            serve(mode, requests(1000.0, 1, "host" if mode.startswith("host") else "device")[:100])
+    res = {"workload": "serve", "sizes": sizes, "duration_s": duration, "slots": slots,
+           "max_batch_pages": max_pages, "hbm_budget_GB": budget / 1e9, "payload": payload, "runs": []}
     for rate in rates:
         for mode in modes:
             s = serve(mode, requests(rate, 5000 + int(rate), "host" if mode.startswith("host") else "device"))
             res["runs"].append({"rate": rate, "mode": mode, **s})
     return res
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_oracle_single_thread_cfg0() -> dict:
+    """The oracle on the 256^2 page (Sauvola win 15, k 0.5) with one OpenMP
+    thread, in a child process (OMP_NUM_THREADS is read when the runtime
+    starts)."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import oracle, pagegen\n"
+            "oracle.build(force=False)\n"
+            "job = pagegen.config0()[0]\n"
+            "oracle.binarize(job.img, job.win, job.k, job.R, job.rule)\n"
+            "t = []\n"
+            "for _ in range(5):\n"
+            "    t0 = time.perf_counter(); oracle.binarize(job.img, job.win, job.k, job.R, job.rule)\n"
+            "    t.append(time.perf_counter() - t0)\n"
+            "print(min(t), oracle.num_threads())\n") % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    sec, threads = out.stdout.split()[-2:]
+    return {"ms": float(sec) * 1e3, "threads": int(threads), "pixels": 256 * 256,
+            "gpix_s": 256 * 256 / float(sec) / 1e9}
+
+
+def run_latency_cfg0(reps: int = 50) -> dict:
+    """Isolated single-launch latency on the 256^2 page (Sauvola win 15): each
+    launch alone on an idle GPU, bracketed by events (device time) and by host
+    time from the call to the end of its synchronisation."""
+    import torch
+
+    import pagegen
+    import paper_1210_3165_amd as bz
+    job = pagegen.config0()[0]
+    img = torch.from_numpy(job.img).cuda()
+    out = torch.empty_like(img)
+    k = _f32(job.k)
+    dev_us, host_us = [], []
+    for _ in range(reps + 5):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        bz.binarize(img, job.win, k, job.R, job.rule, out=out)
+        e1.record()
+        e1.synchronize()
+        host_us.append((time.perf_counter() - t0) * 1e6)
+        dev_us.append(e0.elapsed_time(e1) * 1e3)
+    dev_us, host_us = np.array(dev_us[5:]), np.array(host_us[5:])
+    return {"page": "256x256 gray, Sauvola win 15", "reps": reps,
+            "device_us_p50": float(np.percentile(dev_us, 50)), "device_us_p90": float(np.percentile(dev_us, 90)),
+            "host_us_p50": float(np.percentile(host_us, 50)), "host_us_p90": float(np.percentile(host_us, 90))}
+
+
+def run_copy_stream(dev, mib: int = 1024, reps: int = 5) -> float:
+    """Achievable streaming bandwidth: one copy kernel over a buffer of `mib`
+    MiB (read + write bytes per second), no per-buffer launches."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device=dev)
+    b = torch.empty(n, dtype=torch.uint8, device=dev)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbps
+
+
+def compact_serve(res: dict) -> list:
+    return [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+             if k in ("rate", "mode", "requests", "mean_batch", "p50_ms", "p99_ms", "gpix_s", "req_s")}
+            for r in res["runs"]]
+
+
+def compact_batch(res: dict) -> dict:
+    out = {"pages": res["pages"], "pixels": res["pixels"]}
+    for mode in ("per_image", "batch_direct", "batch_graph"):
+        out[mode + "_gpix_s"] = round(res[mode]["gpix_s"], 2)
+    out["identical"] = res["batch_direct"]["identical_to_per_image"] and res["batch_graph"]["identical_to_per_image"]
+    return out
 
 
 def run_otsu_workload(reps: int, pool_mb: int) -> dict:
@@ -375,6 +490,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--pool-mb", type=int, default=1024, help="rotating buffer pool size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="page4096: skip the batch, serve, latency and copy figures added to the line")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--lds-cap", type=int, default=0,
@@ -492,6 +609,8 @@ def main() -> int:
     torch.cuda.synchronize()
     copy_gbps = 2 * px * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
+    copy_stream_gbps = run_copy_stream(dev)
+
     traffic = measured_traffic()
     step_ms = total_ms / args.steps
     rec = {
@@ -528,10 +647,34 @@ def main() -> int:
         },
         "cases": cases,
         "copy_GBps": copy_gbps,
+        "copy_stream_GBps": copy_stream_gbps,
         "wall_s": t_wall,
     }
+    # which roof limits the dominant kernel: the instruction-issue (VALU)
+    # fraction against the HBM fraction, from the measured figures
+    valu = rec["roofline"]["valu"]
+    hbm_frac = rec["roofline"]["frac"]
+    rec["roofline"]["limited_by"] = ("valu-issue/latency" if valu and valu["frac"] > hbm_frac else "hbm")
+    rec["roofline"]["frac_of_copy_stream"] = achieved / copy_stream_gbps
+    if not args.no_extras:
+        del ins, outs
+        torch.cuda.empty_cache()
+        extras = {}
+        extras["latency_cfg0"] = run_latency_cfg0()
+        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5))
+        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3))
+        torch.cuda.empty_cache()
+        extras["serve"] = compact_serve(run_serve_workload([200.0, 1000.0, 5000.0], 1.0, 4, 32, "both"))
+        torch.cuda.empty_cache()
+        extras["serve_saturation"] = {
+            "pages": "4096x4096 gray, Sauvola win 31 (16.8 Mpx per request)",
+            "runs": compact_serve(run_serve_workload([16000.0], 0.5, 4, 32, "device", sizes="page4096",
+                                                     warm=False))}
+        rec["extras"] = extras
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = run_cpu_baseline(page, args.cpu_budget)
+        rec["cpu_baseline"]["cpu_model"] = cpu_model()
+        rec["cpu_baseline"]["single_thread_cfg0"] = run_oracle_single_thread_cfg0()
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -6,9 +6,10 @@ recorded after that write (``Request.ready``), and its batch waits for it on
 the GPU.  The server:
 
 * admits them in arrival order while the HBM footprint of everything
-  admitted and not yet finished stays within a budget (footprint of a page =
-  input + output bytes = (C + 1) H W); a request larger than the whole budget
-  is refused;
+  admitted and not yet finished stays within a budget; a request is charged
+  the device bytes its executor holds for it (input plus pooled output, each
+  pooled buffer rounded up to its size class; (C + 1) H W on the simulated
+  device), and a request larger than the whole budget is refused;
 * whenever one of K execution slots is free, turns the admitted, not yet
   dispatched requests into a micro-batch (bounded in pages and pixels) and
   dispatches it, so requests that arrive while other batches run join the
@@ -16,7 +17,15 @@ the GPU.  The server:
   overlap on the device;
 * retires a batch when its completion event fires, releasing its footprint
   and its output buffers, and records each request's latency (arrival to
-  completion on the GPU).
+  completion on the GPU);
+* drops a request that is still waiting (not yet dispatched) when its
+  timeout expires or when it is cancelled (``Server.cancel``), releasing its
+  footprint; work already on the GPU cannot be recalled, so a dispatched
+  request always runs to completion;
+* watches every dispatched batch: one that has not completed ``watchdog_s``
+  seconds after dispatch is declared failed, its requests are reported as
+  such and its slot is retired (never reused), so one stuck batch cannot
+  stall the rest of the stream.
 
 Executors: ``GpuBatchExecutor`` (one persistent-launch batch object and one
 stream per slot), ``GpuSingleExecutor`` (the plain one-launch-per-request
@@ -55,6 +64,9 @@ class Request:
     done: float = math.nan
     refused: bool = False
     slot: int = -1
+    timeout: float = math.inf  # seconds after arrival by which it must be dispatched
+    charge: int = 0            # device bytes admission counted for it
+    status: str = "pending"    # done | refused | timed_out | cancelled | failed
 
     @property
     def footprint(self) -> int:
@@ -105,6 +117,9 @@ class SimClock:
 class ServeStats:
     completed: list = field(default_factory=list)
     refused: list = field(default_factory=list)
+    timed_out: list = field(default_factory=list)
+    cancelled: list = field(default_factory=list)
+    failed: list = field(default_factory=list)
     batches: int = 0
     max_admitted_bytes: int = 0
     max_queue: int = 0
@@ -118,6 +133,9 @@ class ServeStats:
         return {
             "requests": len(self.completed),
             "refused": len(self.refused),
+            "timed_out": len(self.timed_out),
+            "cancelled": len(self.cancelled),
+            "failed": len(self.failed),
             "batches": self.batches,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
@@ -132,11 +150,19 @@ class ServeStats:
 
 class Server:
     def __init__(self, executor, hbm_budget: int, max_batch_pages: int = 64,
-                 max_batch_pixels: int = 64 * 2**20):
+                 max_batch_pixels: int = 64 * 2**20, watchdog_s: float = 10.0):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_pages = int(max_batch_pages)
         self.max_pixels = int(max_batch_pixels)
+        self.watchdog = float(watchdog_s)
+        self._cancel = set()
+
+    def cancel(self, rid: int) -> None:
+        """Cancel request `rid` if it has not been dispatched yet (it is
+        dropped at the next scheduling step; a dispatched request runs to
+        completion).  Safe to call from an ``on_done`` callback."""
+        self._cancel.add(rid)
 
     def run(self, requests, clock, on_done=None) -> ServeStats:
         """Serve `requests` (sorted by arrival or not) on `clock`.  on_done(r)
@@ -149,23 +175,49 @@ class Server:
         admitted = deque()     # admitted, waiting for a slot
         free = list(range(self.ex.slots))
         inflight = {}          # slot -> list of requests
+        started = {}           # slot -> dispatch time of its batch
         used = 0               # admitted footprint bytes
+
+        def drop(r, status, now):
+            r.status = status
+            r.done = now
+            {"timed_out": st.timed_out, "cancelled": st.cancelled}[status].append(r)
+
         while incoming or arrived or admitted or inflight:
             now = clock.now()
             while incoming and incoming[0].arrival <= now:
                 arrived.append(incoming.popleft())
+            # timeouts and cancellations of requests not yet on the GPU
+            for q, admitted_q in ((arrived, False), (admitted, True)):
+                if not q:
+                    continue
+                keep = deque()
+                for r in q:
+                    if r.rid in self._cancel:
+                        drop(r, "cancelled", now)
+                    elif now > r.arrival + r.timeout:
+                        drop(r, "timed_out", now)
+                    else:
+                        keep.append(r)
+                        continue
+                    if admitted_q:
+                        used -= r.charge
+                q.clear()
+                q.extend(keep)
             # admission by footprint, in arrival order
             while arrived:
                 r = arrived[0]
-                if r.footprint > self.budget:
+                r.charge = self.ex.charge(r)
+                if r.charge > self.budget:
                     arrived.popleft()
                     r.refused = True
+                    r.status = "refused"
                     st.refused.append(r)
                     continue
-                if used + r.footprint > self.budget:
+                if used + r.charge > self.budget:
                     break
                 arrived.popleft()
-                used += r.footprint
+                used += r.charge
                 r.admitted = now
                 admitted.append(r)
             st.max_admitted_bytes = max(st.max_admitted_bytes, used)
@@ -184,22 +236,52 @@ class Server:
                     r.slot = slot
                 self.ex.submit(slot, batch, now)
                 inflight[slot] = batch
+                started[slot] = now
                 st.batches += 1
                 st.batch_sizes.append(len(batch))
             # completions, in whatever order they finish
             for slot, t_done in self.ex.poll(now):
+                started.pop(slot, None)
                 for r in inflight.pop(slot):
                     r.done = t_done
-                    used -= r.footprint
+                    r.status = "done"
+                    used -= r.charge
                     st.completed.append(r)
                     if on_done is not None:
                         on_done(r)
                     r.out = None  # the buffer goes back to the pool
                 self.ex.release(slot)
                 free.append(slot)
+            # watchdog: a batch past its deadline is failed and its slot retired
+            for slot in [s_ for s_, t0 in started.items() if now - t0 > self.watchdog]:
+                del started[slot]
+                for r in inflight.pop(slot):
+                    r.status = "failed"
+                    r.done = now
+                    used -= r.charge
+                    st.failed.append(r)
+                self.ex.abandon(slot)
             if not (incoming or arrived or admitted or inflight):
                 break
+            if not free and not inflight:  # every slot retired: nothing can run any more
+                for q in (arrived, admitted):
+                    while q:
+                        r = q.popleft()
+                        r.status = "failed"
+                        r.done = now
+                        st.failed.append(r)
+                while incoming:
+                    r = incoming.popleft()
+                    r.status = "failed"
+                    r.done = now
+                    st.failed.append(r)
+                break
             nxt = self.ex.next_event(now)
+            if started:
+                nxt = min(nxt, min(started.values()) + self.watchdog + 1e-6)
+            for q in (arrived, admitted):
+                if q:
+                    nxt = min(nxt, min(r.arrival + r.timeout for r in q) + 1e-6)
             if incoming:
                 nxt = min(nxt, incoming[0].arrival)
             if nxt > now:
@@ -223,6 +305,7 @@ class FakeExecutor:
         self.jitter = jitter
         self.finish = {}
         self.submitted = []
+        self.abandoned = []
 
     def submit(self, slot, batch, now):
         dur = self.latency + sum(r.pixels for r in batch) / self.rate
@@ -240,31 +323,56 @@ class FakeExecutor:
     def release(self, slot):
         pass
 
+    def charge(self, r) -> int:
+        return r.footprint
+
+    def abandon(self, slot):
+        """The server gave up on the slot's batch (watchdog)."""
+        self.finish.pop(slot, None)
+        self.abandoned.append(slot)
+
     def next_event(self, now):
-        return min(self.finish.values()) if self.finish else now + 1e-3
+        finite = [t for t in self.finish.values() if t != math.inf]
+        return min(finite) if finite else now + 1e-3
+
+
+def _size_class(n: int) -> int:
+    return 1 << max(12, (n - 1).bit_length())
 
 
 class _BufferPool:
-    """Device output buffers in power-of-two size classes, reused after the
-    batch that wrote them retires."""
+    """Device buffers in power-of-two size classes, reused after the batch
+    that used them retires.  Idle buffers are freed (largest first) whenever
+    the pool would otherwise hold more than ``cap`` bytes, so the memory it
+    keeps stays within the server's budget."""
 
-    def __init__(self, device):
+    def __init__(self, device, cap: int = 1 << 62):
         import torch
         self.torch = torch
         self.device = device
+        self.cap = int(cap)
         self.free = {}
         self.bytes = 0
 
+    def _trim(self, need: int) -> None:
+        for cls in sorted(self.free, reverse=True):
+            lst = self.free[cls]
+            while lst and self.bytes + need > self.cap:
+                lst.pop()
+                self.bytes -= cls
+
     def get(self, n: int):
-        cls = 1 << max(12, (n - 1).bit_length())
+        cls = _size_class(n)
         lst = self.free.setdefault(cls, [])
         if lst:
             return lst.pop()
+        self._trim(cls)
         self.bytes += cls
         return self.torch.empty(cls, dtype=self.torch.uint8, device=self.device)
 
     def put(self, buf):
         self.free.setdefault(buf.numel(), []).append(buf)
+        self._trim(0)
 
 
 class _PinnedPool:
@@ -278,7 +386,7 @@ class _PinnedPool:
         self.bytes = 0
 
     def get(self, n: int):
-        cls = 1 << max(12, (n - 1).bit_length())
+        cls = _size_class(n)
         lst = self.free.setdefault(cls, [])
         if lst:
             return lst.pop()
@@ -290,13 +398,13 @@ class _PinnedPool:
 
 
 class _GpuBase:
-    def __init__(self, slots: int, device=None):
+    def __init__(self, slots: int, device=None, pool_cap: int = 1 << 62):
         import torch
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         self.slots = slots
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
-        self.pool = _BufferPool(self.device)
+        self.pool = _BufferPool(self.device, pool_cap)
         self.ev = {}
         self.bufs = {}
         # time reference: GPU timestamps are converted to the server clock
@@ -322,11 +430,15 @@ class _GpuBase:
                 st.wait_event(r.ready)
 
     def _outs(self, slot, batch):
+        # allocated on the slot's stream, where they are written: the caching
+        # allocator then never hands out a block whose last use on another
+        # stream is still queued
         bufs = []
-        for r in batch:
-            b = self.pool.get(r.pixels)
-            bufs.append(b)
-            r.out = b[:r.pixels].view(r.H, r.W)
+        with self.torch.cuda.stream(self.streams[slot]):
+            for r in batch:
+                b = self.pool.get(r.pixels)
+                bufs.append(b)
+                r.out = b[:r.pixels].view(r.H, r.W)
         self.bufs[slot] = bufs
 
     def poll(self, now):
@@ -340,6 +452,18 @@ class _GpuBase:
     def release(self, slot):
         for b in self.bufs.pop(slot, []):
             self.pool.put(b)
+
+    def charge(self, r) -> int:
+        """Device bytes a device-resident request holds while admitted: its
+        input (the caller's) and the pooled output buffer (rounded up to its
+        size class)."""
+        return r.C * r.pixels + _size_class(r.pixels)
+
+    def abandon(self, slot):
+        """The server gave up on the slot's batch (watchdog): its buffers stay
+        out of the pool, since the stream may still write them."""
+        self.ev.pop(slot, None)
+        self.bufs.pop(slot, None)
 
     def next_event(self, now):
         return now + 5e-5 if self.ev else now + 1e-3
@@ -359,8 +483,8 @@ class GpuBatchExecutor(_GpuBase):
     pages' tiles over the CUs)."""
 
     def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None,
-                 min_persistent: int = 4):
-        super().__init__(slots, device)
+                 min_persistent: int = 4, pool_cap: int = 1 << 62):
+        super().__init__(slots, device, pool_cap)
         from . import Batch
         self.batches = [Batch(max_pages, lds_cap=lds_cap, device=self.device) for _ in range(slots)]
         self.min_persistent = int(min_persistent)
@@ -406,10 +530,15 @@ class GpuHostBatchExecutor(GpuBatchExecutor):
     A request completes when its result is in host memory."""
 
     def __init__(self, slots: int = 4, max_pages: int = 64, lds_cap: int = 0, device=None,
-                 min_persistent: int = 4):
-        super().__init__(slots, max_pages, lds_cap, device, min_persistent)
+                 min_persistent: int = 4, pool_cap: int = 1 << 62):
+        super().__init__(slots, max_pages, lds_cap, device, min_persistent, pool_cap)
         self.host_pool = _PinnedPool()
         self.host_bufs = {}
+
+    def charge(self, r) -> int:
+        """Device bytes of a host-origin request: pooled input and output
+        buffers, each rounded up to its size class."""
+        return _size_class(r.C * r.pixels) + _size_class(r.pixels)
 
     def submit(self, slot, batch, now):
         torch = self.torch
