@@ -178,7 +178,10 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
  * binarize_batch_run -- plan the pages (host, into the pinned table), then
  *   enqueue on `stream`: table copy, counter reset, persistent kernel.  With
  *   use_graph != 0 the three are captured into a HIP graph on the first call
- *   and replayed afterwards (the table contents change, the graph does not).
+ *   and replayed afterwards (the table contents change, the graph does not;
+ *   it is captured again when n_pages rounded up to a power of two, at
+ *   least 64, changes).  Pages of every channel count, rule and tile width
+ *   share the one launch; items run longest tile first.
  *   Waits for the previous run of the same object before rewriting its
  *   table.  Every img/out pointer must stay valid until the stream reaches
  *   the end of the run.  Errors as for binarize (per page), BZ_ERR_SHAPE for

@@ -5,7 +5,8 @@
 // Every tile of every page is one work item.  Items are numbered page by page
 // (page p owns items [item0[p], item0[p] + tiles[p])); a workgroup takes the
 // next item from a device counter, finds its page by binary search over
-// item0, and runs the same tile code as the single-page kernel.  Results are
+// item0, and runs the tile code of that page's variant (tile width,
+// channels, rule) -- the same code as the single-page kernel.  Results are
 // bit-identical to binarizing each page alone: the arithmetic of a pixel does
 // not depend on which tile, launch or neighbour page it is computed with.
 #include <hip/hip_runtime.h>
@@ -27,40 +28,37 @@ using namespace bz;
 
 namespace {
 
-constexpr int kKinds = 8;  // (tile_w == 256) * 4 + (channels == 3) * 2 + rule
+// Tile variant of a page, 0..7: (tile_w == 256) * 4 + (channels == 3) * 2 + rule.
+inline int kind_of(int tile_w, int channels, int rule) { return (tile_w == 256) * 4 + (channels == 3) * 2 + rule; }
 
-// Table header: one item list per tile variant.  Pages of one kind are
-// contiguous in the page array, starting at page0[kind].
 struct BatchHeader {
-    uint32_t n_pages[kKinds];
-    uint32_t n_items[kKinds];
-    uint32_t page0[kKinds];
-    uint32_t pad[8];
+    uint32_t n_pages;
+    uint32_t n_items;
+    uint32_t pad[14];
 };
 
 struct BatchPage {
     PageArgs a;
-    int item0;  // first work item of this page within its kind
-    int pad[3];
+    int item0;  // first work item of this page
+    int kind;   // tile variant, kind_of()
+    int pad[2];
 };
 
-// Persistent workgroups of one tile variant pull items of that variant until
-// its counter passes n_items; every workgroup reaches that exit because the
-// counter only grows.  MINW is the occupancy the register budget is sized for
-// (waves per SIMD): 2 for LDS caps above a quarter of the CU's LDS, 4 below.
-template <int KIND, int MINW>
+// Persistent workgroups pull items until the counter passes n_items; every
+// workgroup reaches that exit because the counter only grows.  One kernel
+// holds all eight tile variants and branches on the page's kind (uniform per
+// workgroup), so pages of every kind share one launch and one queue of
+// items.  MINW is the occupancy the register budget is sized for (waves per
+// SIMD): 2 for LDS caps above a quarter of the CU's LDS, 4 below.
+template <int MINW>
 __global__ void __launch_bounds__(kThreads, MINW)
-    bz_batch_kernel(const BatchHeader *__restrict__ hdr, const BatchPage *__restrict__ all_pages,
-                    uint32_t *__restrict__ counters) {
-    constexpr int TW = (KIND & 4) ? 256 : 128;
-    constexpr int C = (KIND & 2) ? 3 : 1;
-    constexpr int RULE = KIND & 1;
+    bz_batch_kernel(const BatchHeader *__restrict__ hdr, const BatchPage *__restrict__ pages,
+                    uint32_t *__restrict__ counter) {
     extern __shared__ uint4 bz_lds[];
     __shared__ int s_item;
-    const int n_items = (int)hdr->n_items[KIND];
-    const int n_pages = (int)hdr->n_pages[KIND];
-    const BatchPage *pages = all_pages + hdr->page0[KIND];
-    uint32_t *counter = counters + KIND;
+    uint8_t *smem = (uint8_t *)bz_lds;
+    const int n_items = (int)hdr->n_items;
+    const int n_pages = (int)hdr->n_pages;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -75,24 +73,30 @@ __global__ void __launch_bounds__(kThreads, MINW)
             if (pages[mid].item0 <= item) lo = mid;
             else hi = mid - 1;
         }
-        run_tile<TW, C, RULE, false>(pages[lo].a, item - pages[lo].item0, (uint8_t *)bz_lds);
+        const BatchPage &pg = pages[lo];
+        const int tile = item - pg.item0;
+        switch (__builtin_amdgcn_readfirstlane(pg.kind)) {
+            case 0: run_tile<128, 1, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+            case 1: run_tile<128, 1, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+            case 2: run_tile<128, 3, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+            case 3: run_tile<128, 3, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+            case 4: run_tile<256, 1, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+            case 5: run_tile<256, 1, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+            case 6: run_tile<256, 3, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+            default: run_tile<256, 3, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+        }
         __syncthreads();  // the next item restages LDS
     }
 }
 
 using BatchKernel = void (*)(const BatchHeader *, const BatchPage *, uint32_t *);
-const BatchKernel kBatchKernels[2][kKinds] = {
-    {bz_batch_kernel<0, 2>, bz_batch_kernel<1, 2>, bz_batch_kernel<2, 2>, bz_batch_kernel<3, 2>,
-     bz_batch_kernel<4, 2>, bz_batch_kernel<5, 2>, bz_batch_kernel<6, 2>, bz_batch_kernel<7, 2>},
-    {bz_batch_kernel<0, 4>, bz_batch_kernel<1, 4>, bz_batch_kernel<2, 4>, bz_batch_kernel<3, 4>,
-     bz_batch_kernel<4, 4>, bz_batch_kernel<5, 4>, bz_batch_kernel<6, 4>, bz_batch_kernel<7, 4>},
-};
+const BatchKernel kBatchKernels[2] = {bz_batch_kernel<2>, bz_batch_kernel<4>};
 
 // LDS the batch kernels declare statically (the item slot), rounded up.
 constexpr int kStaticLds = 64;
 
-__global__ void bz_counter_reset(uint32_t *counters) {
-    if (threadIdx.x < kKinds) counters[threadIdx.x] = 0u;
+__global__ void bz_counter_reset(uint32_t *counter) {
+    if (threadIdx.x == 0) *counter = 0u;
 }
 
 int fail(hipError_t e) {
@@ -108,6 +112,12 @@ struct Span {
     int page;
 };
 
+// Tile choice and work estimate of one page, for ordering the item list.
+struct PagePlan {
+    double cost;  // estimated time of one of its tiles (arbitrary unit)
+    int tw, th, kind, page;
+};
+
 // Opaque batch object (bz_batch in the C ABI).
 struct bz_batch {
     int max_pages;
@@ -118,10 +128,9 @@ struct bz_batch {
     void *dev_table;     // device copy read by the kernel
     uint32_t *counter;   // device work counter
     hipStream_t cap_stream;
-    hipGraph_t graph;       // captured for the set of kinds in graph_mask
+    hipGraph_t graph;       // captured for tables of up to graph_pages pages
     hipGraphExec_t exec;
-    int graph_mask;
-    int kind_mask;          // kinds present in the last planned batch
+    int graph_pages;
     int variant;            // 0: register budget for 2 workgroups per CU, 1: for 4
     hipEvent_t done;     // completion of the last run (guards the pinned table)
     bool pending;
@@ -129,6 +138,7 @@ struct bz_batch {
     Span *spans;            // host scratch for the alias check: max_pages output spans
     uintptr_t *span_max;    // and the running maximum of their ends
     ImageDesc *descs;       // the checked pages (pitches filled in)
+    PagePlan *plans;        // tile choice and order of the pages
 };
 
 namespace {
@@ -184,71 +194,66 @@ int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
     return BZ_OK;
 }
 
-// Fill header + pages of the table at `mem`, pages grouped by tile variant;
-// returns the total item count in *items and the kinds present in *mask.
+// Table bytes for n pages.
+size_t table_size(int n) { return sizeof(BatchHeader) + (size_t)n * sizeof(BatchPage); }
+
+// Fill header + pages of the table at `mem` and return the item count in
+// *items.  Pages are ordered by the estimated time of one of their tiles,
+// longest first (ties: kind, then the caller's order), so the queue ends
+// with the shortest items and the last workgroups to finish finish close
+// together; pages of one kind stay mostly adjacent.
 int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, Span *spans, uintptr_t *span_max,
-         int *items, int *mask) {
+         PagePlan *plans, int *items) {
     BatchHeader *hdr = (BatchHeader *)mem;
     BatchPage *bp = (BatchPage *)(hdr + 1);
     std::memset(hdr, 0, sizeof(*hdr));
-    // pass 1: validate, choose tiles, count pages per kind
-    int kinds[kKinds] = {0};
     for (int i = 0; i < n; ++i) {
         const bz_page &p = pages[i];
         descs[i] = page_desc(p);
         int rc = check_page(descs[i], p.win, p.k, p.R, p.rule);
         if (rc) return rc;
-        int tw, th;
-        rc = page_tile(p, lds_cap, &tw, &th);
-        if (rc) return rc;
-        const int rule = make_decision(p.rule, p.k, p.R, p.win).rule;
-        kinds[(tw == 256) * 4 + (p.channels == 3) * 2 + rule]++;
+        PagePlan &q = plans[i];
+        if ((rc = page_tile(p, lds_cap, &q.tw, &q.th))) return rc;
+        q.kind = kind_of(q.tw, p.channels, make_decision(p.rule, p.k, p.R, p.win).rule);
+        q.page = i;
+        // rows streamed (with the window's start-up rows) times columns
+        // summed (with the halo); colour pages also convert on staging
+        q.cost = (double)(q.th + p.win - 1) * (double)(q.tw + p.win - 1) * (p.channels == 3 ? 1.5 : 1.0);
     }
     if (int rc = check_cross_alias(descs, n, spans, span_max)) return rc;
-    int fill[kKinds];
-    for (int q = 0, acc = 0; q < kKinds; ++q) {
-        fill[q] = acc;
-        hdr->page0[q] = (uint32_t)acc;
-        hdr->n_pages[q] = (uint32_t)kinds[q];
-        acc += kinds[q];
-    }
-    // pass 2: fill, page order kept within a kind
+    std::sort(plans, plans + n, [](const PagePlan &x, const PagePlan &y) {
+        if (x.cost != y.cost) return x.cost > y.cost;
+        if (x.kind != y.kind) return x.kind < y.kind;
+        return x.page < y.page;
+    });
     long total = 0;
-    long per_kind[kKinds] = {0};
-    *mask = 0;
-    for (int i = 0; i < n; ++i) {
-        const bz_page &p = pages[i];
-        int tw, th;
-        page_tile(p, lds_cap, &tw, &th);
-        const int rule = make_decision(p.rule, p.k, p.R, p.win).rule;
-        const int q = (tw == 256) * 4 + (p.channels == 3) * 2 + rule;
-        BatchPage &e = bp[fill[q]++];
+    for (int j = 0; j < n; ++j) {
+        const PagePlan &q = plans[j];
+        const bz_page &p = pages[q.page];
+        BatchPage &e = bp[j];
         std::memset(&e, 0, sizeof(e));
-        e.a = page_args(descs[i], p.win, p.k, p.R, p.rule, tw, th);
-        e.item0 = (int)per_kind[q];
-        per_kind[q] += e.a.n_tiles;
+        e.a = page_args(descs[q.page], p.win, p.k, p.R, p.rule, q.tw, q.th);
+        e.item0 = (int)total;
+        e.kind = q.kind;
         total += e.a.n_tiles;
-        if (per_kind[q] >= (1L << 31)) return BZ_ERR_SHAPE;
-        *mask |= 1 << q;
+        if (total >= (1L << 31)) return BZ_ERR_SHAPE;
     }
-    for (int q = 0; q < kKinds; ++q) hdr->n_items[q] = (uint32_t)per_kind[q];
-    *items = (int)(total < (1L << 31) ? total : (1L << 31) - 1);
+    hdr->n_pages = (uint32_t)n;
+    hdr->n_items = (uint32_t)total;
+    *items = (int)total;
     return BZ_OK;
 }
 
-// Enqueue table copy, counter reset and one persistent kernel per kind in
-// `mask` (kinds run one after another on the stream).
-int record(bz_batch *b, int mask, hipStream_t st) {
-    hipError_t e = hipMemcpyAsync(b->dev_table, b->host_table, b->table_bytes, hipMemcpyHostToDevice, st);
+// Enqueue the copy of the first `bytes` of the table, the counter reset and
+// the persistent kernel.
+int record(bz_batch *b, size_t bytes, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(b->dev_table, b->host_table, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(bz_counter_reset, dim3(1), dim3(64), 0, st, b->counter);
     const BatchHeader *hdr = (const BatchHeader *)b->dev_table;
     const BatchPage *pg = (const BatchPage *)(hdr + 1);
-    for (int q = 0; q < kKinds; ++q) {
-        if (!(mask & (1 << q))) continue;
-        hipLaunchKernelGGL(kBatchKernels[b->variant][q], dim3((unsigned)b->grid), dim3(kThreads),
-                           (unsigned)b->lds_cap, st, hdr, pg, b->counter);
-    }
+    hipLaunchKernelGGL(kBatchKernels[b->variant], dim3((unsigned)b->grid), dim3(kThreads), (unsigned)b->lds_cap,
+                       st, hdr, pg, b->counter);
     e = hipGetLastError();
     return e == hipSuccess ? BZ_OK : fail(e);
 }
@@ -269,12 +274,11 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
     b->max_pages = max_pages;
     b->lds_cap = lds_cap_bytes;
     b->variant = (lds_cap_bytes + kStaticLds) * 4 <= kMaxLds ? 1 : 0;
-    b->table_bytes = sizeof(BatchHeader) + (size_t)max_pages * sizeof(BatchPage);
+    b->table_bytes = table_size(max_pages);
     hipError_t e = hipSuccess;
     for (int v = 0; v < 2; ++v)
-        for (int q = 0; q < kKinds; ++q)
-            (void)hipFuncSetAttribute((const void *)kBatchKernels[v][q], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      kMaxLds - kStaticLds);
+        (void)hipFuncSetAttribute((const void *)kBatchKernels[v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kMaxLds - kStaticLds);
     (void)hipGetLastError();
     int per_cu = 1 << 30, dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -282,14 +286,12 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
         delete b;
         return fail(e);
     }
-    for (int q = 0; q < kKinds; ++q) {  // the grid that fills the GPU for every kind
-        int pc = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kBatchKernels[b->variant][q], kThreads,
+    {  // the grid that fills the GPU
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kBatchKernels[b->variant], kThreads,
                                                               lds_cap_bytes)) != hipSuccess) {
             delete b;
             return fail(e);
         }
-        if (pc < per_cu) per_cu = pc;
     }
     if (per_cu < 1) {
         delete b;
@@ -301,7 +303,7 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
         return fail(e);
     }
     if ((e = hipMalloc(&b->dev_table, b->table_bytes)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->counter, kKinds * sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMalloc((void **)&b->counter, sizeof(uint32_t))) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
         binarize_batch_destroy(b);
@@ -311,7 +313,8 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
     b->spans = new (std::nothrow) Span[(size_t)max_pages];
     b->span_max = new (std::nothrow) uintptr_t[(size_t)max_pages];
     b->descs = new (std::nothrow) ImageDesc[(size_t)max_pages];
-    if (!b->spans || !b->span_max || !b->descs) {
+    b->plans = new (std::nothrow) PagePlan[(size_t)max_pages];
+    if (!b->spans || !b->span_max || !b->descs || !b->plans) {
         binarize_batch_destroy(b);
         return BZ_ERR_HIP;
     }
@@ -329,13 +332,18 @@ int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_g
         if (e != hipSuccess) return fail(e);
         b->pending = false;
     }
-    int items = 0, mask = 0;
-    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->descs, b->spans, b->span_max, &items, &mask);
+    int items = 0;
+    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->descs, b->spans, b->span_max, b->plans, &items);
     if (rc) return rc;
     b->last_items = items;
-    b->kind_mask = mask;
     if (use_graph) {
-        if (b->exec && b->graph_mask != mask) {  // a different set of kinds: capture again
+        // the graph copies a table of graph_pages pages (a power of two, at
+        // least 64, at most max_pages); capture again when the batch needs
+        // another size
+        int gp = 64;
+        while (gp < n_pages) gp *= 2;
+        if (gp > b->max_pages) gp = b->max_pages;
+        if (b->exec && b->graph_pages != gp) {
             (void)hipGraphExecDestroy(b->exec);
             (void)hipGraphDestroy(b->graph);
             b->exec = nullptr;
@@ -344,7 +352,7 @@ int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_g
         if (!b->exec) {
             hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return fail(e);
-            rc = record(b, mask, b->cap_stream);
+            rc = record(b, table_size(gp), b->cap_stream);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->cap_stream, &g);
             if (rc) {
@@ -354,12 +362,12 @@ int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_g
             if (e != hipSuccess) return fail(e);
             b->graph = g;
             if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return fail(e);
-            b->graph_mask = mask;
+            b->graph_pages = gp;
         }
         hipError_t e = hipGraphLaunch(b->exec, st);
         if (e != hipSuccess) return fail(e);
     } else {
-        rc = record(b, mask, st);
+        rc = record(b, table_size(n_pages), st);
         if (rc) return rc;
     }
     hipError_t e = hipEventRecord(b->done, st);
@@ -433,6 +441,7 @@ void binarize_batch_destroy(bz_batch *b) {
     delete[] b->spans;
     delete[] b->span_max;
     delete[] b->descs;
+    delete[] b->plans;
     delete b;
 }
 

@@ -144,7 +144,10 @@ inline int check_page(ImageDesc &d, int win, float k, float R, int rule) {
 // Default tile for a page on a GPU with `cus` compute units: 256 columns
 // when the window fits, and a height that gives every CU as many tiles as
 // the LDS footprint lets it run at once, at least 64 rows so the win
-// start-up rows stay a modest share of a tile.
+// start-up rows stay a modest share of a tile.  A page too small to give
+// every CU one 64-row tile gets shorter tiles instead (down to 8 rows, about
+// one per CU): its launch is then bound by one workgroup's latency, which
+// shorter tiles cut.
 inline void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
     const int w = tile_fits(256, win) ? 256 : 128;
     int per_cu = kMaxLds / tile_lds_bytes(w, win);
@@ -152,10 +155,12 @@ inline void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) 
     if (per_cu > 8) per_cu = 8;  // 8 x 4 waves fill a CU
     const long target = (long)cus * per_cu;
     const long tiles_x = (W + w - 1) / w;
-    long h = ((long)H * tiles_x + target - 1) / target;
-    h = (h + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep;
+    const long rows = (long)H * tiles_x;  // tile rows of the page, all columns of tiles
+    auto r8 = [](long v) { return (v + kRowsPerStep - 1) / kRowsPerStep * kRowsPerStep; };
+    long h = r8((rows + target - 1) / target);
     const long hmin = 64;
     if (h < hmin) h = hmin;
+    if (tiles_x * ((H + hmin - 1) / hmin) < cus) h = r8((rows + cus - 1) / cus);  // small page
     if (h > 4096) h = 4096;
     *tw = w;
     *th = (int)h;
