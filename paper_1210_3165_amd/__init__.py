@@ -125,9 +125,30 @@ def _row_view(t: torch.Tensor, what: str) -> tuple[int, int, int, int]:
 
 
 def _stream_ptr(stream, device) -> int:
-    if stream is None:
-        stream = torch.cuda.current_stream(device)
+    if stream is None:  # the raw handle of the device's current stream, no Stream object
+        idx = torch.device(device).index
+        return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device() if idx is None else idx)
     return stream.cuda_stream
+
+
+class _NoSwitch:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *exc):
+        return False
+
+
+_NO_SWITCH = _NoSwitch()
+
+
+def _on_device(device):
+    """Context that makes `device` current for the library's calls; free when
+    it already is (the common single-GPU case)."""
+    idx = torch.device(device).index
+    if idx is None or idx == torch.cuda.current_device():
+        return _NO_SWITCH
+    return torch.cuda.device(idx)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -164,7 +185,7 @@ def binarize(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule=SAUVO
         raise ValueError("out must be an HxW uint8 tensor on the image's device")
     pitch_out = _row_view(out, "out")[3]
     L = lib()
-    with torch.cuda.device(img.device):
+    with _on_device(img.device):
         s = ctypes.c_void_p(_stream_ptr(stream, img.device))
         if pitch_in != W * C or pitch_out != W:
             if tile is not None:
@@ -203,7 +224,7 @@ def binarize_staged(img: torch.Tensor, win: int, k: float, R: float = 128.0, rul
         _keep_for(stream, img.device, workspace)
     elif workspace.device != img.device or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous tensor on the image's device")
-    with torch.cuda.device(img.device):
+    with _on_device(img.device):
         s = ctypes.c_void_p(_stream_ptr(stream, img.device))
         rc = L.binarize_staged(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule), _ptr(out),
                                _ptr(workspace), workspace.numel() * workspace.element_size(), s)
@@ -228,7 +249,7 @@ def binarize_stats(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule
     }
     _keep_for(stream, dev, *res.values())
     L = lib()
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         s = ctypes.c_void_p(_stream_ptr(stream, dev))
         rc = L.binarize_stats(_ptr(img), H, W, C, int(win), float(k), float(R), _rule(rule),
                               _ptr(res["out"]), _ptr(res["gray"]), _ptr(res["s1"]),
@@ -309,7 +330,7 @@ def batch(jobs, stream: torch.cuda.Stream | None = None) -> None:
     arr = (_Page * len(jobs))()
     for i, job in enumerate(jobs):
         arr[i] = _page_struct(job, i)
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         s = ctypes.c_void_p(_stream_ptr(stream, dev))
         rc = _batch_lib().binarize_batch(arr, len(jobs), s)
     if rc:
@@ -330,7 +351,7 @@ class Batch:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         L = _batch_lib()
         h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
+        with _on_device(self.device):
             rc = L.binarize_batch_create(int(max_pages), int(lds_cap), ctypes.byref(h))
         if rc:
             raise BinarizeError(rc, "binarize_batch_create")
@@ -345,7 +366,7 @@ class Batch:
         arr = (_Page * max(n, 1))()
         for i, job in enumerate(jobs):
             arr[i] = _page_struct(job, i)
-        with torch.cuda.device(self.device):
+        with _on_device(self.device):
             s = ctypes.c_void_p(_stream_ptr(stream, self.device))
             rc = _batch_lib().binarize_batch_run(self._h, arr, n, 1 if use_graph else 0, s)
         if rc:
@@ -436,7 +457,7 @@ class Otsu:
                 or not out.is_contiguous():
             raise ValueError("out must be a contiguous HxW uint8 tensor on the image's device")
         _keep_for(stream, self.device, self.ws)
-        with torch.cuda.device(self.device):
+        with _on_device(self.device):
             s = ctypes.c_void_p(_stream_ptr(stream, self.device))
             rc = _otsu_lib().binarize_otsu(_ptr(img), H, W, C, _ptr(out), _ptr(self.ws),
                                            4 * OTSU_WS_WORDS, s)
@@ -482,7 +503,7 @@ def otsu_noalloc(img: torch.Tensor, out: torch.Tensor | None = None, result: tor
     if result is not None and (result.dtype != torch.int32 or result.numel() < OTSU_WS_KSTAR + 1
                                or result.device != img.device or not result.is_contiguous()):
         raise ValueError("result must be a contiguous int32 tensor of >= 258 words on the image's device")
-    with torch.cuda.device(img.device):
+    with _on_device(img.device):
         s = ctypes.c_void_p(_stream_ptr(stream, img.device))
         rc = _otsu_lib().binarize_otsu_noalloc(_ptr(img), H, W, C, _ptr(out), _ptr(result), s)
     if rc:
@@ -537,7 +558,7 @@ def binarize_gs(img: torch.Tensor, win: int, k: float, Rp: float = 128.0, struct
         for name, dt in (("s1", torch.int32), ("s2", torch.int32), ("n", torch.int32), ("t", torch.float32)):
             planes[name] = torch.empty((H, W), dtype=dt, device=dev)
         _keep_for(stream, dev, *planes.values())
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         s = ctypes.c_void_p(_stream_ptr(stream, dev))
         rc = _gs_lib().binarize_gs(_ptr(img), H, W, C, int(win), float(k), float(Rp), _structure(structure),
                                    _ptr(out), _ptr(planes.get("s1")), _ptr(planes.get("s2")),
@@ -564,7 +585,7 @@ def fmeasure_counts(out: torch.Tensor, gt: torch.Tensor, counts: torch.Tensor | 
     if counts is None:
         counts = torch.empty(3, dtype=torch.int64, device=out.device)
         _keep_for(stream, out.device, counts)
-    with torch.cuda.device(out.device):
+    with _on_device(out.device):
         s = ctypes.c_void_p(_stream_ptr(stream, out.device))
         rc = _gs_lib().binarize_fmeasure_counts(_ptr(out), _ptr(gt), out.numel(), _ptr(counts), s)
     if rc:

@@ -77,6 +77,25 @@ BZ_SDWA_BYTE_OP(byte_sub, "v_sub_u32_sdwa")
 BZ_SDWA_BYTE_OP(byte_add, "v_add_u32_sdwa")
 #undef BZ_SDWA_BYTE_OP
 
+
+// Output byte b of w (b a constant after unrolling) becomes 0x00 on lanes
+// where `dark` holds and 0xff elsewhere; the other bytes of w are kept.  One
+// VALU instruction: a byte-select conditional move on the lane mask.
+#define BZ_PUT_BYTE(BSEL)                                                                               \
+    asm("s_mov_b64 vcc, %3\n\tv_cndmask_b32_sdwa %0, %1, %2, vcc dst_sel:" BSEL                            \
+        " dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"                                        \
+        : "+v"(w)                                                                                          \
+        : "v"(ff), "v"(zero), "s"(m)                                                                       \
+        : "vcc")
+__device__ __forceinline__ void put_out_byte(uint32_t &w, int b, bool dark, uint32_t ff, uint32_t zero) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(dark);
+    if (b == 0) BZ_PUT_BYTE("BYTE_0");
+    else if (b == 1) BZ_PUT_BYTE("BYTE_1");
+    else if (b == 2) BZ_PUT_BYTE("BYTE_2");
+    else BZ_PUT_BYTE("BYTE_3");
+}
+#undef BZ_PUT_BYTE
+
 // ---------------------------------------------------------------- staging
 //
 // A staging job is 16 consecutive pixels of one image row.  Its raw bytes are
@@ -564,10 +583,16 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // 0 .. win-1 of the Vb row).  A uniform, not unrolled loop over
         // 32-entry blocks: reads stay below 32 * ceil(win / 32) <= vbw, and
         // entries at i >= win are masked after the read.
-        uint32_t h1 = 0, h2 = 0;
+        uint32_t h1, h2;
         const int nblk = (win + TPR - 1) / TPR;
+        {
+            const int i = hs;  // block 0, always present
+            const uint32_t z1 = Vb1[hr * VBP + i], z2 = Vb2[hr * VBP + v2_pos<OPT == 8>(i, vbw)];
+            h1 = i < win ? z1 : 0u;
+            h2 = i < win ? z2 : 0u;
+        }
 #pragma unroll 1
-        for (int it = 0; it < nblk; ++it) {
+        for (int it = 1; it < nblk; ++it) {
             const int i = hs + it * TPR;
             const uint32_t z1 = Vb1[hr * VBP + i], z2 = Vb2[hr * VBP + v2_pos<OPT == 8>(i, vbw)];
             h1 += i < win ? z1 : 0u;
@@ -611,19 +636,20 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         uint32_t ow[OPT / 4];
 #pragma unroll
         for (int i = 0; i < OPT / 4; ++i) ow[i] = 0u;
+        const uint32_t kFF = __builtin_amdgcn_readfirstlane(0xffu), kZero = 0u;
         float sqv[OPT];
         if (x_inside && full_rows) {  // uniform: every window of the step and block is win x win
             if (RULE == 0) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
                     const bool dark = dark_sauvola_full(q_full, byte_at(fw, j), b1 + E1[j], b2 + E2[j], sqv[j]);
-                    ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                    put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
                     const bool dark = dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n_full, sqv[j]);
-                    ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                    put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
                 }
             }
         } else {  // clipped windows: n per pixel, no division
@@ -634,7 +660,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 const uint32_t n = (uint32_t)__mul24(nx, ny);
                 const bool dark = RULE == 0 ? dark_sauvola(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j])
                                             : dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n, sqv[j]);
-                ow[j >> 2] |= dark ? 0u : 0xffu << (8 * (j & 3));
+                put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
             }
         }
         // The rows of the next step go into the slots of this step's leaving
