@@ -459,6 +459,17 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // blocks of RB rows are fetched before any of them is stored, so their
     // loads are in flight together instead of one latency per block.
     // The rows of the first step are requested together with the last blocks.
+    //
+    // Wave priorities.  The waves of a CU come from several workgroups, each
+    // of which alternates a short phase that every other wave of it waits
+    // for at a barrier (start-up, vertical pass, the reads that open the
+    // horizontal pass, the staging and stores that close a step) with a long
+    // arithmetic phase (the decisions).  Issuing the waiting-on phases first
+    // (s_setprio 2, then 1) and the arithmetic at priority 0 lets the
+    // arithmetic of some workgroups fill the VALU while others cross their
+    // barriers, instead of all of them queueing behind one another's
+    // decisions.
+    __builtin_amdgcn_s_setprio(2);
     constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
     Stager<C, INT> st[NS];
     Stager<C, INT> pre;  // rows of the next step, in flight while this one computes
@@ -502,6 +513,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
     uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
     if (vcol) {
+#pragma unroll 8
         for (int i = 0; i < win; ++i) {
             const uint32_t w = *(const uint16_t *)(ring + i * rp + c0);
             const uint32_t f0 = w & 0xffu, f1 = w >> 8;
@@ -540,6 +552,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         // ---- vertical pass: two LDS columns per thread, RB rows, no branches
+        __builtin_amdgcn_s_setprio(2);
         if (vcol) {
             int pe = s_in * rp, px = s_out * rp;  // byte offsets of the entering / leaving rows
             uint32_t fn[RB], fo[RB];
@@ -568,6 +581,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(1);
         __syncthreads();
 
         // ---- horizontal pass + threshold: 32 threads per output row.
@@ -613,6 +627,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const uint32_t b1 = half_total(h1i) + s1i - a1;
         const uint32_t b2 = half_total(h2i) + s2i - a2;
 
+        __builtin_amdgcn_s_setprio(0);  // the decisions: fill-in work
         // gray levels of the output row (centre of the window)
         int sy = s_ctr + hr;  // ring slot of this output row
         if (sy >= depth) sy -= depth;
@@ -670,6 +685,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // their loads (issued a step ago) does not also wait for output
         // stores just issued: vector-memory waits count loads and stores
         // together, in order.
+        __builtin_amdgcn_s_setprio(1);
         s_in = s_in + RB >= depth ? s_in + RB - depth : s_in + RB;
         s_out = s_out + RB >= depth ? s_out + RB - depth : s_out + RB;
         s_ctr = s_ctr + RB >= depth ? s_ctr + RB - depth : s_ctr + RB;
