@@ -464,12 +464,13 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // of which alternates a short phase that every other wave of it waits
     // for at a barrier (start-up, vertical pass, the reads that open the
     // horizontal pass, the staging and stores that close a step) with a long
-    // arithmetic phase (the decisions).  Issuing the waiting-on phases first
-    // (s_setprio 2, then 1) and the arithmetic at priority 0 lets the
-    // arithmetic of some workgroups fill the VALU while others cross their
-    // barriers, instead of all of them queueing behind one another's
-    // decisions.
-    __builtin_amdgcn_s_setprio(2);
+    // arithmetic phase (the decisions).  Issuing the waited-on phases first
+    // (s_setprio 3 for the start-up and vertical pass, 2 for the reads that
+    // open the horizontal pass, 1 for the step's end) and the arithmetic at
+    // priority 0 lets the arithmetic of some workgroups fill the VALU while
+    // others cross their barriers, instead of all of them queueing behind
+    // one another's decisions.
+    __builtin_amdgcn_s_setprio(3);
     constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
     Stager<C, INT> st[NS];
     Stager<C, INT> pre;  // rows of the next step, in flight while this one computes
@@ -552,7 +553,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         // ---- vertical pass: two LDS columns per thread, RB rows, no branches
-        __builtin_amdgcn_s_setprio(2);
+        __builtin_amdgcn_s_setprio(3);
         if (vcol) {
             int pe = s_in * rp, px = s_out * rp;  // byte offsets of the entering / leaving rows
             uint32_t fn[RB], fo[RB];
@@ -581,7 +582,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 }
             }
         }
-        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_s_setprio(2);
         __syncthreads();
 
         // ---- horizontal pass + threshold: 32 threads per output row.
