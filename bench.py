@@ -211,9 +211,10 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int, paylo
     launches on `slots` streams) and in the plain form (one launch per
     request); host-origin payloads (pinned host in and out, copies on the
     slots' streams) batched and one request per batch.  sizes: "config4"
-    (the served mix: 0.1-16 Mpx, gray or RGB, odd win 15-151) or "page4096"
-    (every request a 4096^2 gray page, Sauvola win 31: the size at which a
-    few thousand requests per second approach the GPU's capacity)."""
+    (the served mix: 0.1-16 Mpx, gray or RGB, odd win 15-151), "page4096"
+    (every request a 4096^2 gray page, Sauvola win 31: tens of thousands of
+    requests per second reach the GPU's capacity) or "page512" (512^2 gray
+    pages, Sauvola win 31: per-request launch and host costs dominate)."""
     import torch
 
     import pagegen
@@ -231,13 +232,14 @@ def run_serve_workload(rates, duration: float, slots: int, max_pages: int, paylo
     def stream(rate, seed):
         if sizes == "config4":
             return pagegen.config4_stream(rate, duration, seed)
+        side = 4096 if sizes == "page4096" else 512
         rng = np.random.default_rng(seed)
         t, out = 0.0, []
         while True:
             t += rng.exponential(1.0 / rate)
             if t >= duration or len(out) >= 10_000:
                 return out
-            out.append((t, 4096, 4096, 1, 31, 0.5))
+            out.append((t, side, side, 1, 31, 0.5))
 
     def requests(rate, seed, where):
         rng = np.random.default_rng(seed)
@@ -661,15 +663,25 @@ def main() -> int:
         torch.cuda.empty_cache()
         extras = {}
         extras["latency_cfg0"] = run_latency_cfg0()
-        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5))
-        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3))
+        # batch LDS caps and tile heights as the autotuner picks them for
+        # these shapes (4 workgroups per CU for the RGB A4 set; 2 for the
+        # uneven set, whose widest windows need 80 KiB)
+        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5, 40896, 256))
+        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3, 81856, 256))
         torch.cuda.empty_cache()
         extras["serve"] = compact_serve(run_serve_workload([200.0, 1000.0, 5000.0], 1.0, 4, 32, "both"))
         torch.cuda.empty_cache()
+        # offered loads above what the GPU can finish: completed requests
+        # per second is the capacity of each mode
         extras["serve_saturation"] = {
-            "pages": "4096x4096 gray, Sauvola win 31 (16.8 Mpx per request)",
-            "runs": compact_serve(run_serve_workload([16000.0], 0.5, 4, 32, "device", sizes="page4096",
+            "pages": "4096x4096 gray, Sauvola win 31 (16.8 Mpx per request), offered 60000 req/s",
+            "runs": compact_serve(run_serve_workload([60000.0], 0.15, 4, 32, "device", sizes="page4096",
                                                      warm=False))}
+        torch.cuda.empty_cache()
+        extras["serve_small"] = {
+            "pages": "512x512 gray, Sauvola win 31 (0.26 Mpx per request)",
+            "runs": compact_serve(run_serve_workload([20000.0, 200000.0], 0.05, 4, 32, "device",
+                                                     sizes="page512", warm=True))}
         rec["extras"] = extras
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = run_cpu_baseline(page, args.cpu_budget)

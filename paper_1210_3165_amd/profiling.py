@@ -133,27 +133,34 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, worklo
     }
 
 
-# Counters of the instruction-mix record; SQ_INSTS_VALU is required.
+# Counters of the instruction-mix record (one pass); SQ_INSTS_VALU is
+# required.  A second pass may add the wave-state counters (SQ_WAVE_CYCLES,
+# SQ_WAIT_ANY, ...), which the record then carries too.
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
                "SQ_INSTS_VMEM_WR", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
 
 
-def valu(sq_csv: str, kernel: str, pixels: int, workload: str, commands: list[str],
+def valu(sq_csvs, kernel: str, pixels: int, workload: str, commands: list[str],
          sources: tuple[str, ...]) -> dict:
-    """Mean instruction counts per dispatch of the kernels whose name contains
-    `kernel`, and VALU lane instructions per output pixel (wave instructions
-    x 64 lanes / pixels per dispatch)."""
+    """Mean counter values per dispatch of the kernels whose name contains
+    `kernel`, over one or more SQ counter runs (every counter found in them),
+    and VALU lane instructions per output pixel (wave instructions x 64
+    lanes / pixels per dispatch)."""
     if pixels <= 0:
         raise SystemExit("pixels per dispatch must be positive")
+    if isinstance(sq_csvs, str):
+        sq_csvs = [sq_csvs]
     name, means = None, {}
-    for c in SQ_COUNTERS:
-        vals = []
-        for (n, _), vs in _counter(sq_csv, c).items():
-            if kernel in n:
-                vals += vs
-                name = n
-        if vals:
-            means[c] = statistics.mean(vals)
+    for path in sq_csvs:
+        counters = sorted({r["Counter_Name"] for r in _rows(path)})
+        for c in counters:
+            vals = []
+            for (n, _), vs in _counter(path, c).items():
+                if kernel in n:
+                    vals += vs
+                    name = n
+            if vals:
+                means[c] = statistics.mean(vals)
     if "SQ_INSTS_VALU" not in means:
         raise SystemExit(f"no SQ_INSTS_VALU rows for a kernel matching {kernel!r}")
     return {
@@ -185,7 +192,7 @@ def main(argv=None) -> int:
     f.add_argument("--command", action="append", default=[])
     f.add_argument("--sources", default="binarize.hip,bz_common.hpp,bz_tile.hpp")
     v = sub.add_parser("valu")
-    v.add_argument("sq_csv")
+    v.add_argument("sq_csv", nargs="+")
     v.add_argument("--kernel", required=True, help="substring of the kernel name")
     v.add_argument("--pixels", type=int, required=True, help="output pixels per dispatch")
     v.add_argument("--workload", required=True)
