@@ -292,6 +292,26 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def gpu_sclk_mhz() -> list:
+    """Current shader clock (MHz) of every GPU the driver lists, from the
+    amdgpu power-state tables in sysfs (the level marked '*'); empty when
+    they cannot be read."""
+    import glob
+    import re
+    out = []
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as fh:
+                for line in fh:
+                    if line.rstrip().endswith("*"):
+                        m = re.search(r"(\d+)\s*Mhz", line, re.IGNORECASE)
+                        if m:
+                            out.append(int(m.group(1)))
+        except OSError:
+            continue
+    return out
+
+
 def run_oracle_single_thread_cfg0() -> dict:
     """The oracle on the 256^2 page (Sauvola win 15, k 0.5) with one OpenMP
     thread, in a child process (OMP_NUM_THREADS is read when the runtime
@@ -588,6 +608,7 @@ def main() -> int:
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
+    sclk = gpu_sclk_mhz()  # right after the timed launches
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
@@ -650,6 +671,7 @@ def main() -> int:
         "cases": cases,
         "copy_GBps": copy_gbps,
         "copy_stream_GBps": copy_stream_gbps,
+        "gpu_sclk_mhz_after_timed": sclk,
         "wall_s": t_wall,
     }
     # which roof limits the dominant kernel: the instruction-issue (VALU)

@@ -38,6 +38,17 @@ def _short(name: str) -> str:
     return name.replace("(anonymous namespace)::", "").replace("void ", "")
 
 
+def _pct(v, q: float) -> float:
+    """q-th percentile of v by linear interpolation between order statistics."""
+    s = sorted(v)
+    if len(s) == 1:
+        return s[0]
+    x = (len(s) - 1) * q / 100.0
+    i = int(x)
+    j = min(i + 1, len(s) - 1)
+    return s[i] + (s[j] - s[i]) * (x - i)
+
+
 def trace_summary(d: str, prefix: str, title: str, command: str, note: str = "",
                   only: tuple[str, ...] = ("bz_", "otsu_", "__amd_rocclr_copyBuffer")) -> str:
     stats = _rows(f"{d}/{prefix}_kernel_stats.csv")
@@ -61,8 +72,9 @@ def trace_summary(d: str, prefix: str, title: str, command: str, note: str = "",
         groups[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
         meta[key] = (r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
     out += ["", "## per launch shape (kernel_trace.csv)", "",
-            "| Kernel | grid threads | workgroup | LDS bytes | VGPR | SGPR | launches | mean us | median us |",
-            "|---|---|---|---|---|---|---|---|---|"]
+            "| Kernel | grid threads | workgroup | LDS bytes | VGPR | SGPR | launches | mean us | median us "
+            "| p10 us | p90 us |",
+            "|---|---|---|---|---|---|---|---|---|---|---|"]
     per_name = defaultdict(list)
     for key in groups:
         per_name[key[0]].append(key)
@@ -73,13 +85,14 @@ def trace_summary(d: str, prefix: str, title: str, command: str, note: str = "",
             lds, vg, sg = meta[keys[0]]
             out.append(f"| `{name}` | {len(keys)} shapes, {min(k[1] for k in keys)}..{max(k[1] for k in keys)} | "
                        f"{keys[0][2]} | {lds} | {vg} | {sg} | {len(v)} | {statistics.mean(v):.1f} | "
-                       f"{statistics.median(v):.1f} |")
+                       f"{statistics.median(v):.1f} | {_pct(v, 10):.1f} | {_pct(v, 90):.1f} |")
             continue
         for key in keys:
             v = groups[key]
             lds, vg, sg = meta[key]
             out.append(f"| `{key[0]}` | {key[1]} | {key[2]} | {lds} | {vg} | {sg} | {len(v)} | "
-                       f"{statistics.mean(v):.1f} | {statistics.median(v):.1f} |")
+                       f"{statistics.mean(v):.1f} | {statistics.median(v):.1f} | {_pct(v, 10):.1f} | "
+                       f"{_pct(v, 90):.1f} |")
     return "\n".join(out) + "\n"
 
 

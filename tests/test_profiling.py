@@ -88,3 +88,12 @@ def test_bench_refuses_more_than_one_gpu():
         r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *extra], capture_output=True,
                            text=True, timeout=120, env={**os.environ, **env})
         assert r.returncode == 2 and "one GPU only" in r.stderr, (extra, env, r.stderr)
+
+
+def test_percentile_matches_numpy():
+    import numpy as np
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 5, 40):
+        v = list(rng.uniform(1, 100, n))
+        for q in (10, 50, 90):
+            assert abs(profiling._pct(v, q) - float(np.percentile(v, q))) < 1e-9
