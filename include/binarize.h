@@ -325,9 +325,12 @@ int binarize_gs(const uint8_t *img, int H, int W_img, int channels, int win,
 int binarize_fmeasure_counts(const uint8_t *out, const uint8_t *gt, int64_t npx,
                              unsigned long long *counts, void *stream);
 
-/* LDS bytes one workgroup of the given tile width needs for a window, or
- * BZ_ERR_TILE if that tile cannot hold the window. */
-int binarize_tile_lds(int tile_w, int win);
+/* LDS bytes one workgroup of the given tile width needs for a window and a
+ * channel count (1 or 3: gray pages keep three 8-row blocks of input rows in
+ * LDS, colour pages a ring of win + 8 or more rows), or BZ_ERR_TILE if that
+ * tile cannot hold the window (BZ_ERR_WINDOW, BZ_ERR_CHANNELS for arguments
+ * out of range). */
+int binarize_tile_lds(int tile_w, int win, int channels);
 
 /* Default tile shape binarize/binarize_async pick for a problem. */
 int binarize_default_tile(int H, int W_img, int channels, int win,

@@ -60,7 +60,7 @@ def lib() -> ctypes.CDLL:
     L.binarize_tuned.argtypes = [vp, i, i, i, i, f, f, i, vp, i, i, vp]
     L.binarize_stats.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, vp, vp, vp, vp, vp]
     L.binarize_default_tile.argtypes = [i, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
-    L.binarize_tile_lds.argtypes = [i, i]
+    L.binarize_tile_lds.argtypes = [i, i, i]
     L.binarize_staged.argtypes = [vp, i, i, i, i, f, f, i, vp, vp, ctypes.c_size_t, vp]
     L.binarize_pitched.argtypes = [vp, i, i, i, ctypes.c_int64, i, f, f, i, vp, ctypes.c_int64, vp]
     L.binarize_staged_workspace_size.argtypes = [i, i]
@@ -259,10 +259,10 @@ def binarize_stats(img: torch.Tensor, win: int, k: float, R: float = 128.0, rule
     return res
 
 
-def tile_lds(tile_w: int, win: int) -> int | None:
-    """LDS bytes a workgroup of this tile width needs for the window, or None
-    if the tile cannot hold it."""
-    rc = lib().binarize_tile_lds(int(tile_w), int(win))
+def tile_lds(tile_w: int, win: int, channels: int = 1) -> int | None:
+    """LDS bytes a workgroup of this tile width needs for the window and
+    channel count, or None if the tile cannot hold it."""
+    rc = lib().binarize_tile_lds(int(tile_w), int(win), int(channels))
     return None if rc < 0 else rc
 
 

@@ -48,8 +48,8 @@ def size_bucket(n: float) -> int:
     return max(0, int(round(math.log2(max(n, 1)))))
 
 
-def tile_fits(tile_w: int, win: int, cap: int = 160 * 1024) -> bool:
-    need = tile_lds(tile_w, win)
+def tile_fits(tile_w: int, win: int, cap: int = 160 * 1024, channels: int = 1) -> bool:
+    need = tile_lds(tile_w, win, channels)
     return need is not None and need <= cap
 
 
@@ -122,7 +122,7 @@ class Tuner:
         best, best_ms = None, float("inf")
         results = {}
         for tw, th in SINGLE_TILES:
-            if not tile_fits(tw, win):
+            if not tile_fits(tw, win, channels=C):
                 continue
             ms = self._time(lambda: binarize(img, win, 0.5, 128.0, rule, out=out, tile=(tw, th)))
             results[f"{tw}x{th}"] = round(ms, 4)
@@ -184,8 +184,8 @@ class Tuner:
         pages = [(self._page(h, w, c), torch.empty((h, w), dtype=torch.uint8, device=self.device), win)
                  for h, w, c, win in sample]
         caps = [LDS_2_PER_CU]
-        if all(tile_fits(256 if tile_fits(256, win, LDS_4_PER_CU) else 128, win, LDS_4_PER_CU)
-               for _, _, _, win in sample):
+        if all(tile_fits(256 if tile_fits(256, win, LDS_4_PER_CU, c) else 128, win, LDS_4_PER_CU, c)
+               for _, _, c, win in sample):
             caps.append(LDS_4_PER_CU)
         best, best_ms, results = None, float("inf"), {}
         for cap in caps:

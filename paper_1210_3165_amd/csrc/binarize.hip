@@ -44,9 +44,9 @@ int device_cus() {
 
 Region plane(const void *p, size_t bytes) { return Region{(uintptr_t)p, 1, (int64_t)bytes, (int64_t)bytes}; }
 
-template <int TW, int C, int RULE, bool STATS>
+template <int TW, int C, int RULE, bool STATS, bool BLK>
 int launch_t(const PageArgs &a, int lds, hipStream_t st) {
-    auto kern = bz_page_kernel<TW, C, RULE, STATS>;
+    auto kern = bz_page_kernel<TW, C, RULE, STATS, BLK>;
     static std::once_flag once[kMaxDevices];
     once_per_device(once, [&] {
         // allow the full 160 KB of gfx950 LDS for dynamic shared memory
@@ -60,7 +60,9 @@ int launch_t(const PageArgs &a, int lds, hipStream_t st) {
 
 template <int TW, int C, int RULE>
 int launch_s(const PageArgs &a, bool stats, int lds, hipStream_t st) {
-    return stats ? launch_t<TW, C, RULE, true>(a, lds, st) : launch_t<TW, C, RULE, false>(a, lds, st);
+    if (C == 1 && a.blocks)  // gray page in the blocks layout
+        return stats ? launch_t<TW, 1, RULE, true, true>(a, lds, st) : launch_t<TW, 1, RULE, false, true>(a, lds, st);
+    return stats ? launch_t<TW, C, RULE, true, false>(a, lds, st) : launch_t<TW, C, RULE, false, false>(a, lds, st);
 }
 
 template <int TW, int C>
@@ -95,9 +97,11 @@ int run(ImageDesc d, int win, float k, float R, int rule, int tile_w, int tile_h
                 if (planes[j] && regions_overlap(r, plane(planes[j], sizes[j]))) return BZ_ERR_ALIAS;
         }
     }
-    if (tile_w <= 0 || tile_h <= 0) pick_default_tile(d.H, d.W, win, device_cus(), &tile_w, &tile_h);
-    if ((rc = check_tile(tile_w, tile_h, win))) return rc;
-    PageArgs a = page_args(d, win, k, R, rule, tile_w, tile_h);
+    const int cus = device_cus();
+    if (tile_w <= 0 || tile_h <= 0) pick_default_tile(d.H, d.W, d.C, win, cus, &tile_w, &tile_h);
+    if ((rc = check_tile(tile_w, tile_h, win, d.C))) return rc;
+    const bool blocks = use_blocks(d.H, d.W, d.C, win, tile_w, tile_h, cus);
+    PageArgs a = page_args(d, win, k, R, rule, tile_w, tile_h, blocks);
     if (stats) {
         a.gray = gray;
         a.s1 = s1;
@@ -106,7 +110,8 @@ int run(ImageDesc d, int win, float k, float R, int rule, int tile_w, int tile_h
         a.t = t;
     }
     const int kernel_rule = make_decision(rule, k, R, win).rule;
-    return launch(a, tile_w, d.C, kernel_rule, stats, tile_lds_bytes(tile_w, win), (hipStream_t)stream);
+    return launch(a, tile_w, d.C, kernel_rule, stats, tile_lds_bytes(tile_w, win, d.C, blocks),
+                  (hipStream_t)stream);
 }
 
 ImageDesc contiguous(const uint8_t *img, int H, int W, int C, uint8_t *out) {
@@ -150,10 +155,11 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels, int win, 
                stream);
 }
 
-int binarize_tile_lds(int tile_w, int win) {
+int binarize_tile_lds(int tile_w, int win, int channels) {
     if (check_window(win)) return BZ_ERR_WINDOW;
-    if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
-    return tile_lds_bytes(tile_w, win);
+    if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
+    if (!tile_fits(tile_w, win, channels)) return BZ_ERR_TILE;
+    return tile_lds_bytes(tile_w, win, channels);
 }
 
 int binarize_default_tile(int H, int W_img, int channels, int win, int *tile_w, int *tile_h) {
@@ -161,7 +167,7 @@ int binarize_default_tile(int H, int W_img, int channels, int win, int *tile_w, 
     if (H < 1 || W_img < 1) return BZ_ERR_SHAPE;
     if (channels != 1 && channels != 3) return BZ_ERR_CHANNELS;
     if (check_window(win)) return BZ_ERR_WINDOW;
-    pick_default_tile(H, W_img, win, device_cus(), tile_w, tile_h);
+    pick_default_tile(H, W_img, channels, win, device_cus(), tile_w, tile_h);
     return BZ_OK;
 }
 

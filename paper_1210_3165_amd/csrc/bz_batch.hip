@@ -183,12 +183,15 @@ int check_cross_alias(const ImageDesc *descs, int n, Span *spans, uintptr_t *spa
 int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
     int w = p.tile_w, h = p.tile_h;
     if (w == 0) {
-        w = (tile_fits(256, p.win) && tile_lds_bytes(256, p.win) <= lds_cap) ? 256 : 128;
+        w = (tile_fits(256, p.win, p.channels, false) && tile_lds_bytes(256, p.win, p.channels, false) <= lds_cap)
+                ? 256
+                : 128;
     }
     if (h == 0) h = 128;
     if (w != 128 && w != 256) return BZ_ERR_TILE;
     if (h < kRowsPerStep || h > 4096 || h % kRowsPerStep) return BZ_ERR_TILE;
-    if (!tile_fits(w, p.win) || tile_lds_bytes(w, p.win) > lds_cap) return BZ_ERR_TILE;
+    if (!tile_fits(w, p.win, p.channels, false) || tile_lds_bytes(w, p.win, p.channels, false) > lds_cap)
+        return BZ_ERR_TILE;
     *tw = w;
     *th = h;
     return BZ_OK;
@@ -232,7 +235,7 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, 
         const bz_page &p = pages[q.page];
         BatchPage &e = bp[j];
         std::memset(&e, 0, sizeof(e));
-        e.a = page_args(descs[q.page], p.win, p.k, p.R, p.rule, q.tw, q.th);
+        e.a = page_args(descs[q.page], p.win, p.k, p.R, p.rule, q.tw, q.th, false);
         e.item0 = (int)total;
         e.kind = q.kind;
         total += e.a.n_tiles;
@@ -268,7 +271,7 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
     if (max_pages < 1 || max_pages > (1 << 20)) return BZ_ERR_SHAPE;
     // default: two workgroups per CU with their static LDS
     if (lds_cap_bytes <= 0) lds_cap_bytes = kMaxLds / 2 - kStaticLds;
-    if (lds_cap_bytes < tile_lds_bytes(128, 1) || lds_cap_bytes > kMaxLds - kStaticLds) return BZ_ERR_TILE;
+    if (lds_cap_bytes < tile_lds_bytes(128, 1, 1, false) || lds_cap_bytes > kMaxLds - kStaticLds) return BZ_ERR_TILE;
     bz_batch *b = new (std::nothrow) bz_batch();
     if (!b) return BZ_ERR_HIP;
     b->max_pages = max_pages;

@@ -51,6 +51,7 @@ struct PageArgs {
     int rp;           // LDS ring row pitch in bytes (multiple of 16)
     int depth;        // ring depth in rows
     int row_aligned;  // input rows 16-byte aligned and a multiple of 16 pixels, output rows 8-byte aligned
+    int blocks;       // gray page in the blocks layout (see gray_blocks)
 };
 
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -68,25 +69,53 @@ BZ_HD inline int ring_depth(int win) {
     const int hi = win - 1 - win / 2;
     return (win + kRowsPerStep > hi + 2 * kRowsPerStep) ? win + kRowsPerStep : hi + 2 * kRowsPerStep;
 }
-BZ_HD inline int ring_bytes(int tile_w, int win) {
-    return round_up(ring_depth(win) * ring_pitch(tile_w, win) + 16, 16);
-}
 // Width of the Vb rows: the tile, or the whole first window if that is wider.
 BZ_HD inline int vb_width(int tile_w, int win) { return round_up(win > tile_w ? win : tile_w, 32); }
 // Row pitches of the V arrays: the entries a row needs, then kTrash trash
 // entries that take the writes of the columns the row does not need, so every
 // column writes at one fixed offset per row (the few lanes that write trash
-// share an entry at most four to a wave).  16 keeps a 256-column win-15 tile
-// within 32 KiB of LDS, five workgroups per CU.  For 256-column tiles
-// vb_width is always 256.
+// share an entry at most four to a wave).  For 256-column tiles vb_width is
+// always 256.
 constexpr int kTrash = 16;
 BZ_HD inline int va_pitch(int tile_w) { return tile_w + kTrash; }
 BZ_HD inline int vb_pitch(int tile_w, int win) { return vb_width(tile_w, win) + kTrash; }
-// LDS layout: ring | Va1 [RB][va_pitch] u16 | Vb1 [RB][vb_pitch] u16 |
-// Va2 [RB][va_pitch] u32 | Vb2 [RB][vb_pitch] u32
-BZ_HD inline int tile_lds_bytes(int tile_w, int win) {
+BZ_HD inline int v_bytes(int tile_w, int win) {
     const int pa = va_pitch(tile_w), pb = vb_pitch(tile_w, win);
-    return ring_bytes(tile_w, win) + kRowsPerStep * (pa * 2 + pb * 2 + pa * 4 + pb * 4);
+    return kRowsPerStep * (pa * 2 + pb * 2 + pa * 4 + pb * 4);
+}
+BZ_HD inline int rows_bytes(int rows, int tile_w, int win) { return round_up(rows * ring_pitch(tile_w, win) + 16, 16); }
+
+// Two layouts of the input rows in LDS.  The ring holds every row the
+// window spans (depth rows), so each input byte is staged once per tile (and
+// converted to gray once); its footprint grows with the window.  The blocks
+// layout of a gray page holds three blocks of RB rows: the step's entering
+// rows, its leaving rows and its window centres, each staged from global
+// memory (an input row is read up to three times per tile, the second and
+// third time from L2), so the footprint does not depend on the window; at
+// start-up the first win rows are staged kStartRows at a time into the whole
+// of the tile's LDS and summed.  A gray tile takes the blocks layout when the
+// ring would allow fewer than four workgroups per CU (the occupancy of the
+// narrow windows): staging three blocks costs more than staging one row set,
+// so the ring is kept where it does not limit occupancy.  Both layouts give
+// identical bytes.  The batched launch keeps the ring for every page (its
+// one kernel holds every tile variant; `allow_blocks` false).
+constexpr int kGrayBlocks = 3;
+constexpr int kStartRows = 4 * kRowsPerStep;
+BZ_HD inline int ring_layout_lds(int tile_w, int win) { return rows_bytes(ring_depth(win), tile_w, win) + v_bytes(tile_w, win); }
+BZ_HD inline bool gray_blocks(int tile_w, int win, int channels, bool allow_blocks = true) {
+    return allow_blocks && channels == 1 && ring_layout_lds(tile_w, win) > kMaxLds / 4;
+}
+BZ_HD inline int ring_rows(int tile_w, int win, int channels, bool allow_blocks = true) {
+    return gray_blocks(tile_w, win, channels, allow_blocks) ? kGrayBlocks * kRowsPerStep : ring_depth(win);
+}
+// LDS layout: rows (ring or blocks) | Va1 [RB][va_pitch] u16 |
+// Vb1 [RB][vb_pitch] u16 | Va2 [RB][va_pitch] u32 | Vb2 [RB][vb_pitch] u32,
+// and in the blocks layout at least kStartRows rows of the row pitch.
+BZ_HD inline int tile_lds_bytes(int tile_w, int win, int channels, bool allow_blocks = true) {
+    if (!gray_blocks(tile_w, win, channels, allow_blocks)) return ring_layout_lds(tile_w, win);
+    const int b = rows_bytes(kGrayBlocks * kRowsPerStep, tile_w, win) + v_bytes(tile_w, win);
+    const int s = rows_bytes(kStartRows, tile_w, win);
+    return b > s ? b : s;
 }
 
 // Position of entry x in a V2 row of `width` entries.  Thread h of a row group
@@ -128,10 +157,10 @@ inline void once_per_device(std::once_flag (&flags)[kMaxDevices], F &&f) {
 #endif
 
 // Does this tile configuration fit the hardware?
-inline bool tile_fits(int tile_w, int win) {
+inline bool tile_fits(int tile_w, int win, int channels, bool allow_blocks = true) {
     if (tile_w != 128 && tile_w != 256) return false;
     if (ring_pitch(tile_w, win) > kMaxCols) return false;
-    return tile_lds_bytes(tile_w, win) <= kMaxLds;
+    return tile_lds_bytes(tile_w, win, channels, allow_blocks) <= kMaxLds;
 }
 
 }  // namespace bz

@@ -148,9 +148,9 @@ inline int check_page(ImageDesc &d, int win, float k, float R, int rule) {
 // every CU one 64-row tile gets shorter tiles instead (down to 8 rows, about
 // one per CU): its launch is then bound by one workgroup's latency, which
 // shorter tiles cut.
-inline void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) {
-    const int w = tile_fits(256, win) ? 256 : 128;
-    int per_cu = kMaxLds / tile_lds_bytes(w, win);
+inline void pick_default_tile(int H, int W, int C, int win, int cus, int *tw, int *th) {
+    const int w = tile_fits(256, win, C) ? 256 : 128;
+    int per_cu = kMaxLds / tile_lds_bytes(w, win, C);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 8) per_cu = 8;  // 8 x 4 waves fill a CU
     const long target = (long)cus * per_cu;
@@ -166,16 +166,30 @@ inline void pick_default_tile(int H, int W, int win, int cus, int *tw, int *th) 
     *th = (int)h;
 }
 
-inline int check_tile(int tile_w, int tile_h, int win) {
+// Whether a single-page launch of this tile shape takes the blocks layout:
+// the window makes it eligible (gray_blocks) and the page has more tiles than
+// the ring layout's occupancy runs at once on `cus` CUs.  With fewer tiles
+// the ring's occupancy costs nothing and its start-up (one pass over the
+// first win rows, no barriers between blocks) is the cheaper one.
+inline bool use_blocks(int H, int W, int C, int win, int tile_w, int tile_h, int cus) {
+    if (!gray_blocks(tile_w, win, C)) return false;
+    const long tiles = (long)((W + tile_w - 1) / tile_w) * ((H + tile_h - 1) / tile_h);
+    const long ring_slots = (long)cus * (kMaxLds / ring_layout_lds(tile_w, win));
+    return tiles > ring_slots;
+}
+
+inline int check_tile(int tile_w, int tile_h, int win, int C) {
     if (tile_w != 128 && tile_w != 256) return BZ_ERR_TILE;
     if (tile_h < kRowsPerStep || tile_h > 4096 || tile_h % kRowsPerStep) return BZ_ERR_TILE;
-    if (!tile_fits(tile_w, win)) return BZ_ERR_TILE;
+    if (!tile_fits(tile_w, win, C)) return BZ_ERR_TILE;
     return BZ_OK;
 }
 
 // Kernel arguments of one checked page for a given tile shape.  The page
-// must have passed check_page (pitches filled in) and the tile check_tile.
-inline PageArgs page_args(const ImageDesc &d, int win, float k, float R, int rule, int tile_w, int tile_h) {
+// must have passed check_page (pitches filled in) and the tile check_tile
+// (or the batch's own tile check, with allow_blocks false).
+inline PageArgs page_args(const ImageDesc &d, int win, float k, float R, int rule, int tile_w, int tile_h,
+                          bool allow_blocks = true) {
     const Decision q = make_decision(rule, k, R, win);
     PageArgs a;
     a.img = d.img;
@@ -199,7 +213,8 @@ inline PageArgs page_args(const ImageDesc &d, int win, float k, float R, int rul
     a.tiles_x = (d.W + tile_w - 1) / tile_w;
     a.n_tiles = a.tiles_x * ((d.H + tile_h - 1) / tile_h);
     a.rp = ring_pitch(tile_w, win);
-    a.depth = ring_depth(win);
+    a.depth = ring_rows(tile_w, win, d.C, allow_blocks);
+    a.blocks = gray_blocks(tile_w, win, d.C, allow_blocks) ? 1 : 0;
     a.row_aligned = (((uintptr_t)d.img & 15) == 0 && d.pitch_in % 16 == 0 && ((int64_t)d.W * d.C) % 16 == 0 &&
                      ((uintptr_t)d.out & 7) == 0 && d.pitch_out % 8 == 0)
                         ? 1

@@ -213,6 +213,15 @@ struct Stager {
         }
     }
 
+    // Store into rows `rows`, `rows` + rp, ... (no ring wrap).
+    __device__ __forceinline__ void store_rows(const PageArgs &a, uint8_t *rows, int nrows, int xr0,
+                                               bool clamp) const {
+        if (job_row >= nrows) return;
+        uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
+        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
+        *(uint4 *)(rows + job_row * a.rp + 16 * job_q) = v;
+    }
+
     __device__ __forceinline__ void store(const PageArgs &a, uint8_t *ring, int slot0, int nrows, int xr0,
                                           bool clamp) const {
         if (job_row >= nrows) return;
@@ -426,7 +435,7 @@ __device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, u
     }
 }
 
-template <int TW, int C, int RULE, bool STATS, bool INT>
+template <int TW, int C, int RULE, bool STATS, bool INT, bool BLK>
 __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_t *smem) {
     constexpr int RB = kRowsPerStep;
     constexpr int TPR = kThreadsPerRow;
@@ -445,7 +454,11 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     constexpr int VAP = TW + kTrash;                        // va_pitch
     const int VBP = TW == 256 ? 256 + kTrash : vbw + kTrash;  // vb_pitch (constant for 256 columns)
     uint8_t *ring = smem;
-    uint16_t *Va1 = (uint16_t *)(smem + ring_bytes(TW, win));
+    uint16_t *Va1 = (uint16_t *)(smem + rows_bytes(depth, TW, win));
+    // blocks layout (gray pages with wide windows): the step's entering,
+    // leaving and centre rows; otherwise the ring of depth rows
+    constexpr bool blocks = C == 1 && BLK;
+    uint8_t *const blkE = smem, *const blkL = smem + RB * rp, *const blkC = smem + 2 * RB * rp;
     uint16_t *Vb1 = Va1 + RB * VAP;
     uint32_t *Va2 = (uint32_t *)(Vb1 + RB * VBP);
     uint32_t *Vb2 = Va2 + RB * VAP;
@@ -455,11 +468,6 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // extra word a chunk may read past its last byte all lie inside the row.
     const bool clamp = !INT && (xr0 < 0 || xr0 + rp + 4 > a.W);
 
-    // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1.  Several
-    // blocks of RB rows are fetched before any of them is stored, so their
-    // loads are in flight together instead of one latency per block.
-    // The rows of the first step are requested together with the last blocks.
-    //
     // Wave priorities.  The waves of a CU come from several workgroups, each
     // of which alternates a short phase that every other wave of it waits
     // for at a barrier (start-up, vertical pass, the reads that open the
@@ -471,30 +479,96 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // others cross their barriers, instead of all of them queueing behind
     // one another's decisions.
     __builtin_amdgcn_s_setprio(3);
-    constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
-    Stager<C, INT> st[NS];
-    Stager<C, INT> pre;  // rows of the next step, in flight while this one computes
-    pre.init(a);
-#pragma unroll
-    for (int u = 0; u < NS; ++u) st[u].init(a);
-    for (int r0 = 0; r0 < win; r0 += NS * RB) {
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int rr = r0 + u * RB;
-            if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
-        }
-        if (r0 + NS * RB >= win) pre.fetch(a, Y0 + hi, RB, xr0, clamp);
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int rr = r0 + u * RB;
-            if (rr < win) st[u].store(a, ring, rr, min(RB, win - rr), xr0, clamp);
-        }
-    }
-    __syncthreads();
 
     // ---- vertical-pass ownership: LDS columns c0 = 2 tid and c0 + 1
     const int c0 = 2 * tid;
     const bool vcol = c0 < rp;
+    uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
+    auto add_rows = [&](const uint8_t *rows, int nr) {  // column sums of nr rows, rp apart
+        if (vcol) {
+#pragma unroll 8
+            for (int i = 0; i < nr; ++i) {
+                const uint32_t w = *(const uint16_t *)(rows + i * rp + c0);
+                const uint32_t f0 = w & 0xffu, f1 = w >> 8;
+                v1[0] += f0;
+                v2[0] += f0 * f0;
+                v1[1] += f1;
+                v2[1] += f1 * f1;
+            }
+        }
+    };
+
+    // Rows of the next step, in flight while this one computes: the
+    // entering rows (and in the blocks layout the leaving and centre rows
+    // too).
+    Stager<C, INT> pre, pre_l, pre_c;
+    pre.init(a);
+    if (blocks) {
+        pre_l.init(a);
+        pre_c.init(a);
+        // Rounds of kStartRows rows staged into the whole LDS and summed.
+        constexpr int NS = kStartRows / RB;
+        Stager<C, INT> st[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) st[u].init(a);
+        for (int r0 = 0; r0 < win; r0 += kStartRows) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int rr = r0 + u * RB;
+                if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
+            }
+            if (r0 + kStartRows >= win) {  // the first step's blocks
+                pre.fetch(a, Y0 + hi, RB, xr0, clamp);
+                pre_l.fetch(a, base, RB, xr0, clamp);
+                pre_c.fetch(a, Y0, RB, xr0, clamp);
+            }
+            if (r0 > 0) __syncthreads();  // the previous round is summed
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int rr = r0 + u * RB;
+                if (rr < win) st[u].store_rows(a, smem + u * RB * rp, min(RB, win - rr), xr0, clamp);
+            }
+            __syncthreads();
+            add_rows(smem, min(kStartRows, win - r0));
+        }
+        __syncthreads();  // start-up rows summed: the blocks may be written
+        pre.store_rows(a, blkE, RB, xr0, clamp);
+        pre_l.store_rows(a, blkL, RB, xr0, clamp);
+        if (Y0 + RB < Yend) {
+            pre.fetch(a, Y0 + RB + hi, RB, xr0, clamp);
+            pre_l.fetch(a, Y0 + RB - lo - 1, RB, xr0, clamp);
+        }
+        // pre_c holds the first step's centre rows: stored during its vertical pass
+    } else {
+        // ---- start-up: rows [Y0-lo-1, Y0+hi-1] give V at row Y0-1.  Several
+        // blocks of RB rows are fetched before any of them is stored, so their
+        // loads are in flight together instead of one latency per block.
+        // The rows of the first step are requested together with the last
+        // blocks, and go in behind the start-up rows (slots the start-up
+        // reads do not touch).
+        constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
+        Stager<C, INT> st[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) st[u].init(a);
+        for (int r0 = 0; r0 < win; r0 += NS * RB) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int rr = r0 + u * RB;
+                if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
+            }
+            if (r0 + NS * RB >= win) pre.fetch(a, Y0 + hi, RB, xr0, clamp);
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int rr = r0 + u * RB;
+                if (rr < win) st[u].store(a, ring, rr, min(RB, win - rr), xr0, clamp);
+            }
+        }
+        __syncthreads();
+        add_rows(ring, win);
+        pre.store(a, ring, win, RB, xr0, clamp);
+        if (Y0 + RB < Yend) pre.fetch(a, Y0 + RB + hi, RB, xr0, clamp);
+    }
+
     // Va index of column c: c - off0 - win + 1; Vb index: c - off0 + 1.
     // Columns whose V is not needed in Va / Vb write to a trash entry of the
     // same row instead, which keeps the vertical pass free of branches and
@@ -512,18 +586,6 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         pb1[h] = wb ? ib : vbw + tr;
         pb2[h] = wb ? v2_pos<OPT == 8>(ib, vbw) : vbw + tr;
     }
-    uint32_t v1[2] = {0u, 0u}, v2[2] = {0u, 0u};
-    if (vcol) {
-#pragma unroll 8
-        for (int i = 0; i < win; ++i) {
-            const uint32_t w = *(const uint16_t *)(ring + i * rp + c0);
-            const uint32_t f0 = w & 0xffu, f1 = w >> 8;
-            v1[0] += f0;
-            v2[0] += f0 * f0;
-            v1[1] += f1;
-            v2[1] += f1 * f1;
-        }
-    }
 
     const int hr = tid / TPR, hs = tid % TPR;
     // Steps whose windows all span win rows, in a 256-column block of the
@@ -540,31 +602,42 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     const uint32_t n_full = (uint32_t)__mul24(win, win);
     const WholeWindow q_full = whole_window(a, n_full);
 
-    // The rows of the first step go in behind the start-up rows (slots the
-    // start-up reads do not touch); the rows of the second step are requested.
-    // Ring slots of the step's first entering row (image row y0 + hi), first
-    // leaving row (y0 - lo - 1) and first output row (y0), advanced by RB per
-    // step; slot 0 holds image row base = Y0 - lo - 1 and depth > win.
+    // Ring layout: slots of the step's first entering row (image row
+    // y0 + hi), first leaving row (y0 - lo - 1) and first output row (y0),
+    // advanced by RB per step; slot 0 holds image row base = Y0 - lo - 1 and
+    // depth > win.
     int s_in = win, s_out = 0, s_ctr = lo + 1;
     const int ring_len = depth * rp;  // bytes of the ring
-    pre.store(a, ring, s_in, RB, xr0, clamp);
-    if (Y0 + RB < Yend) pre.fetch(a, Y0 + RB + hi, RB, xr0, clamp);
     __syncthreads();
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
         // ---- vertical pass: two LDS columns per thread, RB rows, no branches
         __builtin_amdgcn_s_setprio(3);
+        if (blocks) {
+            // this step's centre rows go into the centre block, which the
+            // previous step's horizontal pass has finished reading
+            pre_c.store_rows(a, blkC, RB, xr0, clamp);
+            if (y0 + RB < Yend) pre_c.fetch(a, y0 + RB, RB, xr0, clamp);
+        }
         if (vcol) {
-            int pe = s_in * rp, px = s_out * rp;  // byte offsets of the entering / leaving rows
             uint32_t fn[RB], fo[RB];
+            if (blocks) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                fn[r] = *(const uint16_t *)(ring + pe + c0);
-                fo[r] = *(const uint16_t *)(ring + px + c0);
-                pe += rp;
-                px += rp;
-                pe = pe == ring_len ? 0 : pe;
-                px = px == ring_len ? 0 : px;
+                for (int r = 0; r < RB; ++r) {
+                    fn[r] = *(const uint16_t *)(blkE + r * rp + c0);
+                    fo[r] = *(const uint16_t *)(blkL + r * rp + c0);
+                }
+            } else {
+                int pe = s_in * rp, px = s_out * rp;  // byte offsets of the entering / leaving rows
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    fn[r] = *(const uint16_t *)(ring + pe + c0);
+                    fo[r] = *(const uint16_t *)(ring + px + c0);
+                    pe += rp;
+                    px += rp;
+                    pe = pe == ring_len ? 0 : pe;
+                    px = px == ring_len ? 0 : px;
+                }
             }
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -630,8 +703,8 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
         __builtin_amdgcn_s_setprio(0);  // the decisions: fill-in work
         // gray levels of the output row (centre of the window)
-        int sy = s_ctr + hr;  // ring slot of this output row
-        if (sy >= depth) sy -= depth;
+        int sy = blocks ? 2 * RB + hr : s_ctr + hr;  // LDS row of this output row
+        if (!blocks && sy >= depth) sy -= depth;
         // (X0 is a multiple of 16 and xr0 = X0 - ceil16(lo + 1), so the
         // window centre of column X0 sits at LDS column off0 + lo =
         // ceil16(lo + 1) and each thread's OPT bytes are OPT-aligned.)
@@ -679,20 +752,32 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
             }
         }
-        // The rows of the next step go into the slots of this step's leaving
-        // rows, which no thread reads after the vertical pass (see
-        // ring_depth); the centre rows read above are other slots.  Storing
-        // them here, before this step's output stores, means the wait for
-        // their loads (issued a step ago) does not also wait for output
-        // stores just issued: vector-memory waits count loads and stores
-        // together, in order.
+        // The rows of the next step go where no thread reads during the
+        // horizontal pass: in the blocks layout the entering and leaving
+        // blocks (read by the vertical pass only), in the ring the slots of
+        // this step's leaving rows (see ring_depth).  Storing them here,
+        // before this step's output stores, means the wait for their loads
+        // (issued a step ago) does not also wait for output stores just
+        // issued: vector-memory waits count loads and stores together, in
+        // order.
         __builtin_amdgcn_s_setprio(1);
-        s_in = s_in + RB >= depth ? s_in + RB - depth : s_in + RB;
-        s_out = s_out + RB >= depth ? s_out + RB - depth : s_out + RB;
-        s_ctr = s_ctr + RB >= depth ? s_ctr + RB - depth : s_ctr + RB;
-        if (y0 + RB < Yend) {
-            pre.store(a, ring, s_in, RB, xr0, clamp);
-            if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
+        if (blocks) {
+            if (y0 + RB < Yend) {
+                pre.store_rows(a, blkE, RB, xr0, clamp);
+                pre_l.store_rows(a, blkL, RB, xr0, clamp);
+                if (y0 + 2 * RB < Yend) {
+                    pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
+                    pre_l.fetch(a, y0 + 2 * RB - lo - 1, RB, xr0, clamp);
+                }
+            }
+        } else {
+            s_in = s_in + RB >= depth ? s_in + RB - depth : s_in + RB;
+            s_out = s_out + RB >= depth ? s_out + RB - depth : s_out + RB;
+            s_ctr = s_ctr + RB >= depth ? s_ctr + RB - depth : s_ctr + RB;
+            if (y0 + RB < Yend) {
+                pre.store(a, ring, s_in, RB, xr0, clamp);
+                if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
+            }
         }
         if (y < Yend) {
             if (INT) {  // W is a multiple of 16: the thread's outputs lie wholly inside or outside
@@ -732,20 +817,22 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 // every thread stores its outputs with one store.  Both bodies produce
 // identical bytes.  In either, tiles whose windows all span win columns decide
 // steps whose windows also span win rows with the per-tile constants, and
-// every other step with per-pixel n.
-template <int TW, int C, int RULE, bool STATS>
+// every other step with per-pixel n.  BLK selects the blocks layout of the
+// input rows (gray pages; see gray_blocks), a separate kernel so that each
+// layout gets its own register allocation.
+template <int TW, int C, int RULE, bool STATS, bool BLK = false>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
     if (a.row_aligned)
-        process_tile<TW, C, RULE, STATS, true>(a, tile, smem);
+        process_tile<TW, C, RULE, STATS, true, BLK>(a, tile, smem);
     else
-        process_tile<TW, C, RULE, STATS, false>(a, tile, smem);
+        process_tile<TW, C, RULE, STATS, false, BLK>(a, tile, smem);
 }
 
-template <int TW, int C, int RULE, bool STATS>
+template <int TW, int C, int RULE, bool STATS, bool BLK>
 __global__ void __launch_bounds__(kThreads, 4) bz_page_kernel(PageArgs a) {
     extern __shared__ uint4 bz_lds[];
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    run_tile<TW, C, RULE, STATS>(a, tile, (uint8_t *)bz_lds);
+    run_tile<TW, C, RULE, STATS, BLK>(a, tile, (uint8_t *)bz_lds);
 }
 
 }  // namespace bz

@@ -108,14 +108,35 @@ static void check_images() {
 
 static void check_plans() {
     const int sizes[] = {1, 7, 16, 255, 256, 257, 300, 1024, 3508, 4096, 46340};
-    for (int win = 1; win <= 255; ++win)
-        for (int H : sizes)
-            for (int W : sizes) {
-                int tw = 0, th = 0;
-                pick_default_tile(H, W, win, 256, &tw, &th);
-                CHECK(check_tile(tw, th, win) == BZ_OK, "default tile %dx%d win %d: %d x %d", H, W, win, tw, th);
-                CHECK(tile_lds_bytes(tw, win) <= kMaxLds, "LDS");
-            }
+    for (int C : {1, 3})
+        for (int win = 1; win <= 255; ++win)
+            for (int H : sizes)
+                for (int W : sizes) {
+                    int tw = 0, th = 0;
+                    pick_default_tile(H, W, C, win, 256, &tw, &th);
+                    CHECK(check_tile(tw, th, win, C) == BZ_OK, "default tile %dx%dx%d win %d: %d x %d", H, W, C, win,
+                          tw, th);
+                    CHECK(tile_lds_bytes(tw, win, C) <= kMaxLds, "LDS");
+                    // gray tiles: the start-up rounds fit in the tile's LDS
+                    if (C == 1)
+                        CHECK(tile_lds_bytes(tw, win, 1) >= kStartRows * ring_pitch(tw, win), "gray LDS %d win %d",
+                              tw, win);
+                }
+    // layout choice: narrow windows keep the ring; wide windows take the
+    // blocks layout on a full 4096^2 page but not on a page with few tiles
+    {
+        int tw = 0, th = 0;
+        pick_default_tile(4096, 4096, 1, 15, 256, &tw, &th);
+        CHECK(!use_blocks(4096, 4096, 1, 15, tw, th, 256), "win 15 keeps the ring");
+        pick_default_tile(4096, 4096, 1, 101, 256, &tw, &th);
+        CHECK(use_blocks(4096, 4096, 1, 101, tw, th, 256) && tw == 256 && th == 64, "win 101: blocks, 256x64 (%dx%d)",
+              tw, th);
+        CHECK(tile_lds_bytes(tw, 101, 1, true) <= kMaxLds / 4, "four tiles per CU");
+        pick_default_tile(1000, 1000, 1, 101, 256, &tw, &th);
+        CHECK(!use_blocks(1000, 1000, 1, 101, tw, th, 256), "few tiles: ring");
+        pick_default_tile(4096, 4096, 3, 101, 256, &tw, &th);
+        CHECK(!use_blocks(4096, 4096, 3, 101, tw, th, 256), "colour pages keep the ring");
+    }
     // argument block of an aligned page and of a one-byte-shifted one
     alignas(16) static uint8_t buf[4096 * 2 + 64];
     ImageDesc d{buf, buf + 4096 + 32, 64, 64, 1, 0, 0};

@@ -298,3 +298,18 @@ def test_staged_workspace_size(L):
     L.binarize_staged_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int]
     assert L.binarize_staged_workspace_size(4096, 4096) == 8 * 4096 * 4096
     assert L.binarize_staged_workspace_size(0, 5) == 0
+
+
+def test_tile_lds_by_channels(L):
+    """Gray tiles keep three 8-row blocks of input rows in LDS, so their
+    footprint hardly grows with the window; colour tiles keep a ring of
+    win + 8 rows."""
+    g15, g151 = L.binarize_tile_lds(256, 15, 1), L.binarize_tile_lds(256, 151, 1)
+    c15, c151 = L.binarize_tile_lds(256, 15, 3), L.binarize_tile_lds(256, 151, 3)
+    assert 0 < g15 <= g151 <= 40896  # four workgroups per CU at any window a 256-column tile holds
+    assert g151 - g15 < 8 * 1024
+    assert c151 > 80 * 1024 and c15 > 0
+    assert L.binarize_tile_lds(128, 255, 1) > 0
+    assert L.binarize_tile_lds(256, 15, 2) == -3
+    assert L.binarize_tile_lds(256, 0, 1) == -4
+    assert L.binarize_tile_lds(192, 15, 1) == -9

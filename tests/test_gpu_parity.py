@@ -350,6 +350,31 @@ def test_full_size_4096_full_page(bz, oracle_mod, page4096, rule, win, k):
     assert compare_out(out[ys, xs], ref.out[ys, xs], ref.gray[ys, xs], ref.t[ys, xs])["ok"]
 
 
+@pytest.mark.parametrize("H,W,win,rule,k", [(2048, 2051, 151, 0, 0.5), (4096, 2051, 101, 1, -0.2),
+                                            (2304, 2048, 151, 0, -0.7), (4096, 3100, 61, 0, 1.0)])
+def test_blocks_layout_pages(bz, oracle_mod, page4096, H, W, win, rule, k):
+    """Gray pages with wide windows and more tiles than the win + 8-row ring
+    runs at once take the three-block layout of the input rows (aligned and
+    unaligned bodies: W = 2051 is not a multiple of 16).  Every pixel against
+    the oracle, and bit-identical to the batched launch, which keeps the ring
+    layout for every page."""
+    from oracle.compare import compare_out
+    k = f32(k)
+    img = np.ascontiguousarray(page4096[:H, :W])
+    print(f"blocks layout: {H}x{W} win {win} rule {rule} k {k}", flush=True)
+    timg = torch.from_numpy(img).cuda()
+    out = bz.binarize(timg, win, k, 128.0, rule)
+    ring = torch.empty_like(out)
+    bz.batch([(timg, ring, win, k, 128.0, rule)])
+    torch.cuda.synchronize()
+    out, ring = out.cpu().numpy(), ring.cpu().numpy()
+    assert np.array_equal(out, ring)
+    ref = oracle_mod.binarize(img, win, k, 128.0, rule)
+    rep = compare_out(out, ref.out, ref.gray, ref.t)
+    print("blocks", H, W, win, rep, flush=True)
+    assert rep["ok"], rep
+
+
 def test_rgb_a4_page_full(bz, oracle_mod):
     """One A4 RGB page of the batch workload (3508 x 2480, win 31, k 0.34),
     every pixel against the oracle."""
