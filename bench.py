@@ -600,6 +600,18 @@ def main() -> int:
     # all K steps.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in CASES]
     torch.cuda.synchronize()
+    # shader clock sampled from sysfs by a host thread while the timed
+    # launches run (the host only enqueues; the samples see the busy GPU)
+    import threading
+    clk, clk_stop = [], threading.Event()
+
+    def sample_clock():
+        while not clk_stop.is_set():
+            clk.extend(gpu_sclk_mhz())
+            time.sleep(0.001)
+
+    sampler = threading.Thread(target=sample_clock, daemon=True)
+    sampler.start()
     t_wall = time.perf_counter()
     for i, c in enumerate(CASES):
         ev[i][0].record(stream)
@@ -608,7 +620,10 @@ def main() -> int:
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    sclk = gpu_sclk_mhz()  # right after the timed launches
+    clk_stop.set()
+    sampler.join()
+    sclk = {"samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
+            "min_mhz": min(clk) if clk else None, "max_mhz": max(clk) if clk else None}
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
@@ -671,7 +686,7 @@ def main() -> int:
         "cases": cases,
         "copy_GBps": copy_gbps,
         "copy_stream_GBps": copy_stream_gbps,
-        "gpu_sclk_mhz_after_timed": sclk,
+        "gpu_sclk_during_timed": sclk,
         "wall_s": t_wall,
     }
     # which roof limits the dominant kernel: the instruction-issue (VALU)

@@ -112,17 +112,17 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, worklo
 
     def pick(per, sub):
         vals, grids = [], {}
-        name = None
+        names = set()
         for (n, g), v in per.items():
             if sub in n:
                 vals += v
                 grids.setdefault(g, []).extend(v)
-                name = n
-        return name, vals, grids
+                names.add(n)
+        return sorted(names), vals, grids
 
     cf = [v for (n, _), vs in fetch.items() if n == COPY_KERNEL for v in vs]
     cw = [v for (n, _), vs in write.items() if n == COPY_KERNEL for v in vs]
-    name, kf, grids = pick(fetch, kernel)
+    names, kf, grids = pick(fetch, kernel)
     _, kw, _ = pick(write, kernel)
     if not (cf and cw and kf and kw):
         raise SystemExit("missing copy or kernel dispatches in the counter files")
@@ -130,7 +130,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, worklo
     fs, ws = copy_kib / statistics.median(cf), copy_kib / statistics.median(cw)
     f_raw, w_raw = statistics.mean(kf), statistics.mean(kw)
     return {
-        "kernel": name,
+        "kernel": kernel,
+        "kernels": names,
         "workload": workload,
         "source_sha": kernel_source_sha(sources),
         "fetch_kib_per_dispatch_raw": round(f_raw, 1),
@@ -163,7 +164,7 @@ def valu(sq_csvs, kernel: str, pixels: int, workload: str, commands: list[str],
         raise SystemExit("pixels per dispatch must be positive")
     if isinstance(sq_csvs, str):
         sq_csvs = [sq_csvs]
-    name, means = None, {}
+    names, means = set(), {}
     for path in sq_csvs:
         counters = sorted({r["Counter_Name"] for r in _rows(path)})
         for c in counters:
@@ -171,13 +172,14 @@ def valu(sq_csvs, kernel: str, pixels: int, workload: str, commands: list[str],
             for (n, _), vs in _counter(path, c).items():
                 if kernel in n:
                     vals += vs
-                    name = n
+                    names.add(n)
             if vals:
                 means[c] = statistics.mean(vals)
     if "SQ_INSTS_VALU" not in means:
         raise SystemExit(f"no SQ_INSTS_VALU rows for a kernel matching {kernel!r}")
     return {
-        "kernel": name,
+        "kernel": kernel,
+        "kernels": sorted(names),
         "workload": workload,
         "source_sha": kernel_source_sha(sources),
         "pixels_per_dispatch": pixels,

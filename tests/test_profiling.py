@@ -37,6 +37,7 @@ def test_traffic_scales_by_the_copy_kernel(tmp_path):
     assert rec["bytes_per_launch"] == int((9500.0 * 2 + 16384.0) * 1024)
     assert rec["per_grid_fetch_kib_raw"] == {"131072": 10000.0, "262144": 9000.0}
     assert rec["source_sha"] == kernel_source_sha(("bz_tile.hpp",))
+    assert rec["kernels"] == [KERNEL]
 
 
 def test_traffic_needs_copy_and_kernel_rows(tmp_path):
@@ -54,7 +55,7 @@ def test_valu_lane_ops_per_pixel(tmp_path):
                   (KERNEL, 262144, "SQ_WAVES", 4096.0), (KERNEL, 131072, "SQ_WAVES", 2048.0),
                   (OTHER, 262144, "SQ_INSTS_VALU", 1.0)])
     rec = profiling.valu(str(p), "<256, 1, 0, false>", px, "w", ["cmd"], ("bz_tile.hpp",))
-    assert rec["kernel"] == KERNEL
+    assert rec["kernel"] == "<256, 1, 0, false>" and rec["kernels"] == [KERNEL]
     assert rec["per_dispatch"] == {"SQ_WAVES": 3072.0, "SQ_INSTS_VALU": 11_000_000.0}
     assert rec["valu_lane_ops_per_px"] == round(11_000_000 * 64 / px, 3)
     with pytest.raises(SystemExit):
