@@ -367,8 +367,13 @@ def test_blocks_layout_pages(bz, oracle_mod, page4096, H, W, win, rule, k):
     ring = torch.empty_like(out)
     bz.batch([(timg, ring, win, k, 128.0, rule)])
     torch.cuda.synchronize()
-    out, ring = out.cpu().numpy(), ring.cpu().numpy()
+    # the same page as a row-strided view of the whole 4096-wide page
+    full = torch.from_numpy(page4096).cuda()
+    strided = bz.binarize(full[:H, :W], win, k, 128.0, rule)
+    torch.cuda.synchronize()
+    out, ring, strided = out.cpu().numpy(), ring.cpu().numpy(), strided.cpu().numpy()
     assert np.array_equal(out, ring)
+    assert np.array_equal(out, strided)
     ref = oracle_mod.binarize(img, win, k, 128.0, rule)
     rep = compare_out(out, ref.out, ref.gray, ref.t)
     print("blocks", H, W, win, rep, flush=True)
