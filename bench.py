@@ -292,16 +292,35 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def gpu_sclk_mhz() -> list:
-    """Current shader clock (MHz) of every GPU the driver lists, from the
-    amdgpu power-state tables in sysfs (the level marked '*'); empty when
-    they cannot be read."""
+def gpu_pci_slot(dev: int = 0) -> str | None:
+    """PCI slot name ("0000:xx:yy.z") of a HIP device, from the HIP runtime."""
+    import ctypes
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        buf = ctypes.create_string_buffer(64)
+        if hip.hipDeviceGetPCIBusId(buf, 64, dev) != 0:
+            return None
+        return buf.value.decode().lower()
+    except OSError:
+        return None
+
+
+def gpu_sclk_mhz(slot: str | None) -> list:
+    """Current shader clock (MHz) of the GPU at PCI slot `slot`, from the
+    amdgpu power-state table in sysfs (the level marked '*'); empty when it
+    cannot be read or the card is not found (the host may list GPUs this
+    process does not use)."""
     import glob
     import re
+    if not slot:
+        return []
     out = []
-    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+    for card in sorted(glob.glob("/sys/class/drm/card*/device")):
         try:
-            with open(path) as fh:
+            with open(card + "/uevent") as fh:
+                if f"PCI_SLOT_NAME={slot}" not in fh.read().lower():
+                    continue
+            with open(card + "/pp_dpm_sclk") as fh:
                 for line in fh:
                     if line.rstrip().endswith("*"):
                         m = re.search(r"(\d+)\s*Mhz", line, re.IGNORECASE)
@@ -604,10 +623,11 @@ def main() -> int:
     # launches run (the host only enqueues; the samples see the busy GPU)
     import threading
     clk, clk_stop = [], threading.Event()
+    slot = gpu_pci_slot(dev.index or 0)
 
     def sample_clock():
         while not clk_stop.is_set():
-            clk.extend(gpu_sclk_mhz())
+            clk.extend(gpu_sclk_mhz(slot))
             time.sleep(0.001)
 
     sampler = threading.Thread(target=sample_clock, daemon=True)
@@ -622,7 +642,7 @@ def main() -> int:
     t_wall = time.perf_counter() - t_wall
     clk_stop.set()
     sampler.join()
-    sclk = {"samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
+    sclk = {"pci_slot": slot, "samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
             "min_mhz": min(clk) if clk else None, "max_mhz": max(clk) if clk else None}
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
