@@ -331,6 +331,56 @@ def gpu_sclk_mhz(slot: str | None) -> list:
     return out
 
 
+def sample_sclk_under_load(launch, dev, seconds: float = 0.4) -> dict:
+    """Shader clock while the GPU runs the bench's own launches: an untimed
+    burst of the five cases (about `seconds` long, after the timed region)
+    with a host thread reading sysfs meanwhile.  The timed region itself is
+    too short for the sysfs reads, which take milliseconds each."""
+    import threading
+
+    import torch
+    slot = gpu_pci_slot(dev.index or 0)
+    clk, stop = [], threading.Event()
+
+    def sample():
+        while not stop.is_set():
+            clk.extend(gpu_sclk_mhz(slot))
+            time.sleep(0.002)
+
+    th = threading.Thread(target=sample, daemon=True)
+    t0 = time.perf_counter()
+    th.start()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(40):
+            for c in CASES:
+                launch(c)
+        torch.cuda.synchronize()
+    stop.set()
+    th.join()
+    rec = {"pci_slot": slot, "samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
+           "min_mhz": min(clk) if clk else None, "max_mhz": max(clk) if clk else None,
+           "when": "untimed burst of the bench launches right after the timed region"}
+    if not clk:  # say why: the GPUs whose sysfs entries this process sees
+        rec["sysfs_slots_seen"] = sysfs_gpu_slots()
+    return rec
+
+
+def sysfs_gpu_slots() -> list:
+    """PCI slots of the GPUs listed under /sys/class/drm, with whether their
+    power-state table can be read."""
+    import glob
+    seen = []
+    for card in sorted(glob.glob("/sys/class/drm/card*/device")):
+        try:
+            with open(card + "/uevent") as fh:
+                ps = [x.split("=", 1)[1] for x in fh.read().split() if x.startswith("PCI_SLOT_NAME=")]
+        except OSError:
+            continue
+        readable = os.access(card + "/pp_dpm_sclk", os.R_OK)
+        seen += [f"{p}{'' if readable else ' (no pp_dpm_sclk)'}" for p in ps]
+    return seen
+
+
 def run_oracle_single_thread_cfg0() -> dict:
     """The oracle on the 256^2 page (Sauvola win 15, k 0.5) with one OpenMP
     thread, in a child process (OMP_NUM_THREADS is read when the runtime
@@ -619,19 +669,6 @@ def main() -> int:
     # all K steps.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in CASES]
     torch.cuda.synchronize()
-    # shader clock sampled from sysfs by a host thread while the timed
-    # launches run (the host only enqueues; the samples see the busy GPU)
-    import threading
-    clk, clk_stop = [], threading.Event()
-    slot = gpu_pci_slot(dev.index or 0)
-
-    def sample_clock():
-        while not clk_stop.is_set():
-            clk.extend(gpu_sclk_mhz(slot))
-            time.sleep(0.001)
-
-    sampler = threading.Thread(target=sample_clock, daemon=True)
-    sampler.start()
     t_wall = time.perf_counter()
     for i, c in enumerate(CASES):
         ev[i][0].record(stream)
@@ -640,10 +677,7 @@ def main() -> int:
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    clk_stop.set()
-    sampler.join()
-    sclk = {"pci_slot": slot, "samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
-            "min_mhz": min(clk) if clk else None, "max_mhz": max(clk) if clk else None}
+    sclk = sample_sclk_under_load(launch, dev)
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
@@ -706,7 +740,7 @@ def main() -> int:
         "cases": cases,
         "copy_GBps": copy_gbps,
         "copy_stream_GBps": copy_stream_gbps,
-        "gpu_sclk_during_timed": sclk,
+        "gpu_sclk_under_load": sclk,
         "wall_s": t_wall,
     }
     # which roof limits the dominant kernel: the instruction-issue (VALU)
@@ -720,11 +754,10 @@ def main() -> int:
         torch.cuda.empty_cache()
         extras = {}
         extras["latency_cfg0"] = run_latency_cfg0()
-        # batch LDS caps and tile heights as the autotuner picks them for
-        # these shapes (4 workgroups per CU for the RGB A4 set; 2 for the
-        # uneven set, whose widest windows need 80 KiB)
-        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5, 40896, 256))
-        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3, 81856, 256))
+        # batches at the default LDS cap (each launch of a batch takes the
+        # occupancy its pages' tiles allow) and 256-row tiles
+        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5, 0, 256))
+        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3, 0, 256))
         torch.cuda.empty_cache()
         extras["serve"] = compact_serve(run_serve_workload([200.0, 1000.0, 5000.0], 1.0, 4, 32, "both"))
         torch.cuda.empty_cache()

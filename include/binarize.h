@@ -166,29 +166,43 @@ int binarize_stats(const uint8_t *img, int H, int W_img, int channels,
 
 /*
  * Batched form: many pages of uneven size, channels, window, k, R and rule in
- * ONE persistent launch.  Every tile of every page is a work item that
- * workgroups take from a device counter, so uneven pages leave no idle tail
- * per page; each page's output is bit-identical to binarizing it alone.
+ * a few persistent launches on one stream.  Every tile of every page is a
+ * work item that workgroups take from a device counter, so uneven pages
+ * leave no idle tail per page; each page's output is bit-identical to
+ * binarizing it alone.  Pages are grouped by tile width, input-row layout
+ * and LDS need: each group is one launch whose workgroups reserve the LDS
+ * share of the highest occupancy that holds its tiles (4, 3, 2 or 1
+ * workgroups per CU), so narrow windows keep four workgroups per CU when
+ * wide ones share the batch.  Gray pages whose ring of rows would exceed a
+ * quarter of the CU's LDS take the blocks layout (three 8-row blocks, at
+ * most 38 KiB for any window), as in the single-page kernel.
  *
  * binarize_batch_create -- allocate a batch object for up to max_pages pages:
- *   a device page table, a pinned host staging copy of it, a work counter,
- *   a capture stream, an event and host scratch for checking the pages.  lds_cap_bytes bounds the LDS of one
- *   workgroup (0: 80 KiB, i.e. 2 workgroups per CU); pages whose window
- *   needs more fail with BZ_ERR_TILE.  The only entry points that allocate.
+ *   two sets of a device page table, a pinned host staging copy of it, work
+ *   counters and an event; a capture stream; host scratch for checking the
+ *   pages.
+ *   lds_cap_bytes bounds the LDS of one workgroup (0: 81856, the share of
+ *   two workgroups per CU; at most 163776); a page's tile takes 256 columns
+ *   when that fits the cap, else 128, and pages that fit neither fail with
+ *   BZ_ERR_TILE.  The only entry points that allocate.
  * binarize_batch_run -- plan the pages (host, into the pinned table), then
- *   enqueue on `stream`: table copy, counter reset, persistent kernel.  With
- *   use_graph != 0 the three are captured into a HIP graph on the first call
+ *   enqueue on `stream`: table copy, counter reset, one persistent kernel per
+ *   group of pages (each starts when the previous one ends).  With
+ *   use_graph != 0 these are captured into a HIP graph on the first call
  *   and replayed afterwards (the table contents change, the graph does not;
  *   it is captured again when n_pages rounded up to a power of two, at
- *   least 64, changes).  Pages of every channel count, rule and tile width
- *   share the one launch; items run longest tile first.
- *   Waits for the previous run of the same object before rewriting its
- *   table.  Every img/out pointer must stay valid until the stream reaches
+ *   least 64, or the set of groups changes).  Within a group, items run
+ *   longest tile first.
+ *   An object holds two sets of run buffers (pinned and device table, work
+ *   counters, graph) and uses them in turn: a run waits on the host only
+ *   for the run before the previous one, so planning overlaps the GPU's
+ *   work on the previous run.  Every img/out pointer must stay valid until the stream reaches
  *   the end of the run.  Errors as for binarize (per page), BZ_ERR_SHAPE for
  *   n_pages outside [1, max_pages], BZ_ERR_ALIAS when a page's output
  *   overlaps another page's output or any page's input (the pages run
  *   concurrently; inputs may be shared).
- * binarize_batch_info -- persistent grid size, LDS cap, items of last run.
+ * binarize_batch_info -- persistent grid of 256-column ring pages at four
+ *   workgroups per CU, LDS cap, items of the last run.
  * binarize_batch_destroy -- wait for the last run, free everything.
  */
 typedef struct bz_page {
@@ -208,10 +222,9 @@ typedef struct bz_batch bz_batch; /* opaque batch object */
  * binarize_batch -- the batched form in one call (Sec. 1, Eq. 1, 3, 4;
  * Sec. 2 on every page): validates and plans `pages` and enqueues their
  * persistent launch on `stream`, as binarize_batch_run without a graph.
- * The library keeps two batch objects per device for these calls (created
+ * The library keeps one batch object per device for these calls (created
  * on first use, grown to the largest n_pages seen, kept until the process
- * ends) and uses them in turn; a call waits on the host for the run before
- * the previous one.  Errors as binarize_batch_run; BZ_ERR_NULL for a NULL
+ * ends); a call waits on the host for the run before the previous one.  Errors as binarize_batch_run; BZ_ERR_NULL for a NULL
  * pages array.
  */
 int binarize_batch(const bz_page *pages, int n_pages, void *stream);

@@ -1,14 +1,17 @@
 // bz_batch.hip -- many pages of uneven size, channels, window and rule in
-// one persistent launch (the batched form of the tile kernel), optionally
+// one batched launch (persistent kernels of the tile code), optionally
 // replayed from a captured HIP graph.
 //
-// Every tile of every page is one work item.  Items are numbered page by page
-// (page p owns items [item0[p], item0[p] + tiles[p])); a workgroup takes the
-// next item from a device counter, finds its page by binary search over
-// item0, and runs the tile code of that page's variant (tile width,
-// channels, rule) -- the same code as the single-page kernel.  Results are
-// bit-identical to binarizing each page alone: the arithmetic of a pixel does
-// not depend on which tile, launch or neighbour page it is computed with.
+// Every tile of every page is one work item.  Pages are split into kernel
+// groups by tile width and input-row layout, each group a persistent kernel
+// launched after the previous one on the same stream.  Items are numbered
+// page by page (page p owns items [item0[p], item0[p] + tiles[p])); a
+// workgroup takes the next item of its group from the group's device
+// counter, finds its page by binary search over item0, and runs the tile
+// code of that page's variant (channels, rule) -- the same code as the
+// single-page kernel.  Results are bit-identical to binarizing each page
+// alone: the arithmetic of a pixel does not depend on which tile, launch,
+// layout or neighbour page it is computed with.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,75 +31,124 @@ using namespace bz;
 
 namespace {
 
-// Tile variant of a page, 0..7: (tile_w == 256) * 4 + (channels == 3) * 2 + rule.
-inline int kind_of(int tile_w, int channels, int rule) { return (tile_w == 256) * 4 + (channels == 3) * 2 + rule; }
+// Pages run in launches keyed by kernel group and occupancy class, launched
+// one after another on the caller's stream.  Groups 0 and 1 hold the pages
+// in the ring layout with 256- and 128-column tiles, groups 2..5 the gray
+// pages in the blocks layout (those whose ring would exceed a quarter of
+// the CU's LDS), one group per tile variant: 2 + (tile_w == 256) * 2 + rule.
+// Tile variant of a ring page within its group, 0..3:
+// (channels == 3) * 2 + rule.  The class of a page is the highest number of
+// workgroups per CU (4, 3, 2, 1) whose share of the LDS holds its tile; a
+// launch reserves that share per workgroup, so pages of narrow windows run
+// at four workgroups per CU even when wider ones share the batch.
+constexpr int kGroups = 6;
+constexpr int kClasses = 4;
+constexpr int kLaunches = kGroups * kClasses;  // launch key: group * kClasses + class
+inline int kind_of(int channels, int rule) { return (channels == 3) * 2 + rule; }
+inline bool blk_group(int g) { return g >= 2; }
+inline int group_of(int tile_w, int rule, bool blocks) {
+    return blocks ? 2 + (tile_w == 256) * 2 + rule : (tile_w == 256 ? 0 : 1);
+}
 
+// LDS the batch kernels declare statically (the item slot), rounded up.
+constexpr int kStaticLds = 64;
+// Dynamic LDS of a workgroup of class c (kClasses - c workgroups per CU),
+// a multiple of 16 bytes.
+inline int class_lds(int c) { return (kMaxLds / (kClasses - c) - kStaticLds) & ~15; }
+// Class of a tile that needs `lds` bytes (-1: more than one CU holds).
+inline int class_of(int lds) {
+    for (int c = 0; c < kClasses; ++c)
+        if (lds <= class_lds(c)) return c;
+    return -1;
+}
+
+// Launch L owns pages [page_begin[L], page_begin[L + 1]) and work items
+// [item_begin[L], item_begin[L + 1]).
 struct BatchHeader {
     uint32_t n_pages;
     uint32_t n_items;
-    uint32_t pad[14];
+    uint32_t page_begin[kLaunches + 1];
+    uint32_t item_begin[kLaunches + 1];
+    uint32_t pad[12];
 };
+static_assert(sizeof(BatchHeader) == 256, "header size");
 
 struct BatchPage {
     PageArgs a;
     int item0;  // first work item of this page
-    int kind;   // tile variant, kind_of()
+    int kind;   // tile variant within a ring group, kind_of (blocks groups: one variant each)
     int pad[2];
 };
 
-// Persistent workgroups pull items until the counter passes n_items; every
-// workgroup reaches that exit because the counter only grows.  One kernel
-// holds all eight tile variants and branches on the page's kind (uniform per
-// workgroup), so pages of every kind share one launch and one queue of
-// items.  MINW is the occupancy the register budget is sized for (waves per
-// SIMD): 2 for LDS caps above a quarter of the CU's LDS, 4 below.
-template <int MINW>
+// Persistent workgroups pull items of their launch until its counter passes
+// its end; every workgroup reaches that exit because the counter only grows.
+// A ring group's kernel holds the four ring tile variants of its tile width
+// and branches on the page's kind (uniform per workgroup), so gray and
+// colour pages of either rule share one launch and one queue of items.  A
+// blocks group's kernel holds one variant.  Kernels with more variants
+// spilled registers at four workgroups per CU (all eight ring variants: 10
+// VGPRs; all four blocks variants: 52), as the register allocation of a
+// kernel is that of its costliest variant and the page fields of every
+// variant compete for scalar registers.  Blocks pages read their table
+// entry through the constant address space, whose loads the compiler may
+// repeat instead of keeping every page field in a register (fewer spills).
+// MINW is the occupancy the register budget is sized for (waves per SIMD):
+// 4 for class 0, 2 (which still fits three waves) for the others.
+template <int MINW, int G>
 __global__ void __launch_bounds__(kThreads, MINW)
     bz_batch_kernel(const BatchHeader *__restrict__ hdr, const BatchPage *__restrict__ pages,
-                    uint32_t *__restrict__ counter) {
+                    uint32_t *__restrict__ counters, int launch) {
     extern __shared__ uint4 bz_lds[];
     __shared__ int s_item;
     uint8_t *smem = (uint8_t *)bz_lds;
-    const int n_items = (int)hdr->n_items;
-    const int n_pages = (int)hdr->n_pages;
+    const int page0 = (int)hdr->page_begin[launch], page1 = (int)hdr->page_begin[launch + 1];
+    const int item0 = (int)hdr->item_begin[launch], item1 = (int)hdr->item_begin[launch + 1];
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) s_item = item0 + (int)atomicAdd(counters + launch, 1u);
         __syncthreads();
         // uniform across the workgroup: keep it (and the page search and page
         // fields that follow) in scalar registers
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();  // every thread has read s_item before it is rewritten
-        if (item >= n_items) break;
-        int lo = 0, hi = n_pages - 1;
+        if (item >= item1) break;
+        int lo = page0, hi = page1 - 1;
         while (lo < hi) {  // last page whose first item is <= item
             const int mid = (lo + hi + 1) >> 1;
             if (pages[mid].item0 <= item) lo = mid;
             else hi = mid - 1;
         }
-        const BatchPage &pg = pages[lo];
-        const int tile = item - pg.item0;
-        switch (__builtin_amdgcn_readfirstlane(pg.kind)) {
-            case 0: run_tile<128, 1, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
-            case 1: run_tile<128, 1, BZ_NIBLACK, false>(pg.a, tile, smem); break;
-            case 2: run_tile<128, 3, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
-            case 3: run_tile<128, 3, BZ_NIBLACK, false>(pg.a, tile, smem); break;
-            case 4: run_tile<256, 1, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
-            case 5: run_tile<256, 1, BZ_NIBLACK, false>(pg.a, tile, smem); break;
-            case 6: run_tile<256, 3, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
-            default: run_tile<256, 3, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+        if (G < 2) {
+            constexpr int TW = G == 0 ? 256 : 128;
+            const BatchPage &pg = pages[lo];
+            const int tile = item - pg.item0;
+            switch (__builtin_amdgcn_readfirstlane(pg.kind)) {
+                case 0: run_tile<TW, 1, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+                case 1: run_tile<TW, 1, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+                case 2: run_tile<TW, 3, BZ_SAUVOLA, false>(pg.a, tile, smem); break;
+                default: run_tile<TW, 3, BZ_NIBLACK, false>(pg.a, tile, smem); break;
+            }
+        } else {
+            constexpr int TW = G >= 4 ? 256 : 128;
+            constexpr int RULE = G & 1;
+            typedef const __attribute__((address_space(4))) BatchPage ConstPage;
+            const BatchPage &pg = *(const BatchPage *)((ConstPage *)pages + lo);
+            const int tile = item - pg.item0;
+            run_tile<TW, 1, RULE, false, true>(pg.a, tile, smem);
         }
         __syncthreads();  // the next item restages LDS
     }
 }
 
-using BatchKernel = void (*)(const BatchHeader *, const BatchPage *, uint32_t *);
-const BatchKernel kBatchKernels[2] = {bz_batch_kernel<2>, bz_batch_kernel<4>};
+using BatchKernel = void (*)(const BatchHeader *, const BatchPage *, uint32_t *, int);
+// [group][register budget: 0 for 2 waves per SIMD, 1 for 4]
+const BatchKernel kBatchKernels[kGroups][2] = {
+    {bz_batch_kernel<2, 0>, bz_batch_kernel<4, 0>}, {bz_batch_kernel<2, 1>, bz_batch_kernel<4, 1>},
+    {bz_batch_kernel<2, 2>, bz_batch_kernel<4, 2>}, {bz_batch_kernel<2, 3>, bz_batch_kernel<4, 3>},
+    {bz_batch_kernel<2, 4>, bz_batch_kernel<4, 4>}, {bz_batch_kernel<2, 5>, bz_batch_kernel<4, 5>}};
+inline int budget_of(int c) { return c == 0 ? 1 : 0; }
 
-// LDS the batch kernels declare statically (the item slot), rounded up.
-constexpr int kStaticLds = 64;
-
-__global__ void bz_counter_reset(uint32_t *counter) {
-    if (threadIdx.x == 0) *counter = 0u;
+__global__ void bz_counter_reset(uint32_t *counters) {
+    if (threadIdx.x < kLaunches) counters[threadIdx.x] = 0u;
 }
 
 int fail(hipError_t e) {
@@ -116,25 +168,36 @@ struct Span {
 struct PagePlan {
     double cost;  // estimated time of one of its tiles (arbitrary unit)
     int tw, th, kind, page;
+    int launch;   // launch key: group_of * kClasses + class_of
+};
+
+// What one run reads or writes after it is enqueued.  A batch object holds
+// two and uses them in turn, so the host plans a run while the GPU still
+// executes the one before (it waits only for the run before that, which
+// used the same buffers; runs may go to different streams).
+struct RunBuffers {
+    void *host_table;    // pinned staging copy of header + pages
+    void *dev_table;     // device copy read by the kernels
+    uint32_t *counter;   // device work counters, one per launch key
+    hipGraph_t graph;    // captured for tables of up to graph_pages pages
+    hipGraphExec_t exec;
+    int graph_pages;
+    uint32_t graph_launches;  // launch keys the graph launches (bit L: key L)
+    hipEvent_t done;     // completion of the last run on these buffers
+    bool pending;
 };
 
 // Opaque batch object (bz_batch in the C ABI).
 struct bz_batch {
     int max_pages;
     int lds_cap;
-    int grid;
+    int grid[kLaunches];    // persistent grid of each launch key
     size_t table_bytes;
-    void *host_table;    // pinned staging copy of header + pages
-    void *dev_table;     // device copy read by the kernel
-    uint32_t *counter;   // device work counter
+    RunBuffers buf[2];
+    int cur;                // buffers of the next run
     hipStream_t cap_stream;
-    hipGraph_t graph;       // captured for tables of up to graph_pages pages
-    hipGraphExec_t exec;
-    int graph_pages;
-    int variant;            // 0: register budget for 2 workgroups per CU, 1: for 4
-    hipEvent_t done;     // completion of the last run (guards the pinned table)
-    bool pending;
     int last_items;
+    uint32_t last_launches;   // launch keys the last plan used
     Span *spans;            // host scratch for the alias check: max_pages output spans
     uintptr_t *span_max;    // and the running maximum of their ends
     ImageDesc *descs;       // the checked pages (pitches filled in)
@@ -177,23 +240,26 @@ int check_cross_alias(const ImageDesc *descs, int n, Span *spans, uintptr_t *spa
     return BZ_OK;
 }
 
-// Tile for one page within the batch's LDS cap: the caller's choice if it
-// fits, else 256 columns when the window allows, else 128; tile_h 128 unless
-// given.
-int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
+// Tile, layout and LDS need of one page within the batch's LDS cap: the
+// caller's width if it fits, else 256 columns when the window allows, else
+// 128; tile_h 128 unless given.  Gray pages whose ring would exceed a
+// quarter of the CU's LDS take the blocks layout (as in the single-page
+// kernel, which also weighs the page's tile count: in a batch the pages share
+// the GPU, so occupancy always counts), every other page the ring.
+int page_tile(const bz_page &p, int lds_cap, int *tw, int *th, bool *blk, int *lds) {
+    auto fits = [&](int w) {
+        return tile_fits(w, p.win, p.channels) && tile_lds_bytes(w, p.win, p.channels) <= lds_cap;
+    };
     int w = p.tile_w, h = p.tile_h;
-    if (w == 0) {
-        w = (tile_fits(256, p.win, p.channels, false) && tile_lds_bytes(256, p.win, p.channels, false) <= lds_cap)
-                ? 256
-                : 128;
-    }
+    if (w == 0) w = fits(256) ? 256 : 128;
     if (h == 0) h = 128;
     if (w != 128 && w != 256) return BZ_ERR_TILE;
     if (h < kRowsPerStep || h > 4096 || h % kRowsPerStep) return BZ_ERR_TILE;
-    if (!tile_fits(w, p.win, p.channels, false) || tile_lds_bytes(w, p.win, p.channels, false) > lds_cap)
-        return BZ_ERR_TILE;
+    if (!fits(w)) return BZ_ERR_TILE;
     *tw = w;
     *th = h;
+    *blk = gray_blocks(w, p.win, p.channels);
+    *lds = tile_lds_bytes(w, p.win, p.channels);
     return BZ_OK;
 }
 
@@ -201,12 +267,13 @@ int page_tile(const bz_page &p, int lds_cap, int *tw, int *th) {
 size_t table_size(int n) { return sizeof(BatchHeader) + (size_t)n * sizeof(BatchPage); }
 
 // Fill header + pages of the table at `mem` and return the item count in
-// *items.  Pages are ordered by the estimated time of one of their tiles,
-// longest first (ties: kind, then the caller's order), so the queue ends
-// with the shortest items and the last workgroups to finish finish close
-// together; pages of one kind stay mostly adjacent.
+// *items and the launch keys used in *launches (bit L: key L).  Pages are
+// ordered by launch key, and within a launch by the estimated time of one of
+// their tiles, longest first (ties: kind, then the caller's order), so each
+// launch's queue ends with its shortest items and its last workgroups finish
+// close together; pages of one kind stay mostly adjacent.
 int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, Span *spans, uintptr_t *span_max,
-         PagePlan *plans, int *items) {
+         PagePlan *plans, int *items, uint32_t *launches) {
     BatchHeader *hdr = (BatchHeader *)mem;
     BatchPage *bp = (BatchPage *)(hdr + 1);
     std::memset(hdr, 0, sizeof(*hdr));
@@ -216,8 +283,12 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, 
         int rc = check_page(descs[i], p.win, p.k, p.R, p.rule);
         if (rc) return rc;
         PagePlan &q = plans[i];
-        if ((rc = page_tile(p, lds_cap, &q.tw, &q.th))) return rc;
-        q.kind = kind_of(q.tw, p.channels, make_decision(p.rule, p.k, p.R, p.win).rule);
+        bool blk = false;
+        int lds = 0;
+        if ((rc = page_tile(p, lds_cap, &q.tw, &q.th, &blk, &lds))) return rc;
+        const int rule = make_decision(p.rule, p.k, p.R, p.win).rule;
+        q.kind = kind_of(p.channels, rule);
+        q.launch = group_of(q.tw, rule, blk) * kClasses + class_of(lds);
         q.page = i;
         // rows streamed (with the window's start-up rows) times columns
         // summed (with the halo); colour pages also convert on staging
@@ -225,21 +296,33 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, 
     }
     if (int rc = check_cross_alias(descs, n, spans, span_max)) return rc;
     std::sort(plans, plans + n, [](const PagePlan &x, const PagePlan &y) {
+        if (x.launch != y.launch) return x.launch < y.launch;
         if (x.cost != y.cost) return x.cost > y.cost;
         if (x.kind != y.kind) return x.kind < y.kind;
         return x.page < y.page;
     });
     long total = 0;
+    int l = 0;  // launch boundaries filled so far: page_begin[0..l]
+    *launches = 0;
     for (int j = 0; j < n; ++j) {
         const PagePlan &q = plans[j];
         const bz_page &p = pages[q.page];
+        for (; l < q.launch; ++l) {
+            hdr->page_begin[l + 1] = (uint32_t)j;
+            hdr->item_begin[l + 1] = (uint32_t)total;
+        }
+        *launches |= 1u << q.launch;
         BatchPage &e = bp[j];
         std::memset(&e, 0, sizeof(e));
-        e.a = page_args(descs[q.page], p.win, p.k, p.R, p.rule, q.tw, q.th, false);
+        e.a = page_args(descs[q.page], p.win, p.k, p.R, p.rule, q.tw, q.th, blk_group(q.launch / kClasses));
         e.item0 = (int)total;
         e.kind = q.kind;
         total += e.a.n_tiles;
         if (total >= (1L << 31)) return BZ_ERR_SHAPE;
+    }
+    for (; l < kLaunches; ++l) {
+        hdr->page_begin[l + 1] = (uint32_t)n;
+        hdr->item_begin[l + 1] = (uint32_t)total;
     }
     hdr->n_pages = (uint32_t)n;
     hdr->n_items = (uint32_t)total;
@@ -248,15 +331,21 @@ int plan(const bz_page *pages, int n, int lds_cap, void *mem, ImageDesc *descs, 
 }
 
 // Enqueue the copy of the first `bytes` of the table, the counter reset and
-// the persistent kernel.
-int record(bz_batch *b, size_t bytes, hipStream_t st) {
-    hipError_t e = hipMemcpyAsync(b->dev_table, b->host_table, bytes, hipMemcpyHostToDevice, st);
+// the persistent kernel of each launch key in `launches`, in key order (each
+// starts when the one before has finished), with its class's LDS share per
+// workgroup.
+int record(const bz_batch *b, const RunBuffers &r, size_t bytes, uint32_t launches, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(r.dev_table, r.host_table, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(e);
-    hipLaunchKernelGGL(bz_counter_reset, dim3(1), dim3(64), 0, st, b->counter);
-    const BatchHeader *hdr = (const BatchHeader *)b->dev_table;
+    hipLaunchKernelGGL(bz_counter_reset, dim3(1), dim3(64), 0, st, r.counter);
+    const BatchHeader *hdr = (const BatchHeader *)r.dev_table;
     const BatchPage *pg = (const BatchPage *)(hdr + 1);
-    hipLaunchKernelGGL(kBatchKernels[b->variant], dim3((unsigned)b->grid), dim3(kThreads), (unsigned)b->lds_cap,
-                       st, hdr, pg, b->counter);
+    for (int l = 0; l < kLaunches; ++l) {
+        if (!(launches & (1u << l))) continue;
+        const int g = l / kClasses, c = l % kClasses;
+        hipLaunchKernelGGL(kBatchKernels[g][budget_of(c)], dim3((unsigned)b->grid[l]), dim3(kThreads),
+                           (unsigned)class_lds(c), st, hdr, pg, r.counter, l);
+    }
     e = hipGetLastError();
     return e == hipSuccess ? BZ_OK : fail(e);
 }
@@ -269,50 +358,55 @@ int binarize_batch_create(int max_pages, int lds_cap_bytes, bz_batch **out) {
     if (!out) return BZ_ERR_NULL;
     *out = nullptr;
     if (max_pages < 1 || max_pages > (1 << 20)) return BZ_ERR_SHAPE;
-    // default: two workgroups per CU with their static LDS
-    if (lds_cap_bytes <= 0) lds_cap_bytes = kMaxLds / 2 - kStaticLds;
-    if (lds_cap_bytes < tile_lds_bytes(128, 1, 1, false) || lds_cap_bytes > kMaxLds - kStaticLds) return BZ_ERR_TILE;
+    // default: the share of two workgroups per CU
+    if (lds_cap_bytes <= 0) lds_cap_bytes = class_lds(2);
+    if (lds_cap_bytes < tile_lds_bytes(128, 1, 1, false) || lds_cap_bytes > class_lds(kClasses - 1))
+        return BZ_ERR_TILE;
     bz_batch *b = new (std::nothrow) bz_batch();
     if (!b) return BZ_ERR_HIP;
     b->max_pages = max_pages;
     b->lds_cap = lds_cap_bytes;
-    b->variant = (lds_cap_bytes + kStaticLds) * 4 <= kMaxLds ? 1 : 0;
     b->table_bytes = table_size(max_pages);
     hipError_t e = hipSuccess;
-    for (int v = 0; v < 2; ++v)
-        (void)hipFuncSetAttribute((const void *)kBatchKernels[v], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kMaxLds - kStaticLds);
+    for (int g = 0; g < kGroups; ++g)
+        for (int v = 0; v < 2; ++v)
+            (void)hipFuncSetAttribute((const void *)kBatchKernels[g][v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      kMaxLds - kStaticLds);
     (void)hipGetLastError();
-    int per_cu = 1 << 30, dev = 0, cus = 0;
+    int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
         delete b;
         return fail(e);
     }
-    {  // the grid that fills the GPU
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kBatchKernels[b->variant], kThreads,
-                                                              lds_cap_bytes)) != hipSuccess) {
+    for (int l = 0; l < kLaunches; ++l) {  // the grid that fills the GPU, per launch key
+        const int g = l / kClasses, c = l % kClasses;
+        int per_cu = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kBatchKernels[g][budget_of(c)], kThreads,
+                                                              class_lds(c))) != hipSuccess) {
             delete b;
             return fail(e);
         }
+        if (per_cu < 1) {
+            delete b;
+            return BZ_ERR_TILE;
+        }
+        b->grid[l] = cus * per_cu;
     }
-    if (per_cu < 1) {
-        delete b;
-        return BZ_ERR_TILE;
-    }
-    b->grid = cus * per_cu;
-    if ((e = hipHostMalloc(&b->host_table, b->table_bytes, hipHostMallocDefault)) != hipSuccess) {
-        delete b;
-        return fail(e);
-    }
-    if ((e = hipMalloc(&b->dev_table, b->table_bytes)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->counter, sizeof(uint32_t))) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) {
+    if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
         binarize_batch_destroy(b);
         return fail(e);
     }
-    std::memset(b->host_table, 0, b->table_bytes);
+    for (RunBuffers &r : b->buf) {
+        if ((e = hipHostMalloc(&r.host_table, b->table_bytes, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&r.dev_table, b->table_bytes)) != hipSuccess ||
+            (e = hipMalloc((void **)&r.counter, kLaunches * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming)) != hipSuccess) {
+            binarize_batch_destroy(b);
+            return fail(e);
+        }
+        std::memset(r.host_table, 0, b->table_bytes);
+    }
     b->spans = new (std::nothrow) Span[(size_t)max_pages];
     b->span_max = new (std::nothrow) uintptr_t[(size_t)max_pages];
     b->descs = new (std::nothrow) ImageDesc[(size_t)max_pages];
@@ -329,33 +423,37 @@ int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_g
     if (!b || !pages) return BZ_ERR_NULL;
     if (n_pages < 1 || n_pages > b->max_pages) return BZ_ERR_SHAPE;
     hipStream_t st = (hipStream_t)stream;
-    // the pinned table may still be read by the previous run's copy
-    if (b->pending) {
-        hipError_t e = hipEventSynchronize(b->done);
+    RunBuffers &r = b->buf[b->cur];
+    // these buffers may still be in use by the run before the previous one
+    if (r.pending) {
+        hipError_t e = hipEventSynchronize(r.done);
         if (e != hipSuccess) return fail(e);
-        b->pending = false;
+        r.pending = false;
     }
     int items = 0;
-    int rc = plan(pages, n_pages, b->lds_cap, b->host_table, b->descs, b->spans, b->span_max, b->plans, &items);
+    uint32_t launches = 0;
+    int rc = plan(pages, n_pages, b->lds_cap, r.host_table, b->descs, b->spans, b->span_max, b->plans, &items,
+                  &launches);
     if (rc) return rc;
     b->last_items = items;
+    b->last_launches = launches;
     if (use_graph) {
         // the graph copies a table of graph_pages pages (a power of two, at
-        // least 64, at most max_pages); capture again when the batch needs
-        // another size
+        // least 64, at most max_pages) and makes the launches the plan uses;
+        // capture again when the batch needs another size or other launches
         int gp = 64;
         while (gp < n_pages) gp *= 2;
         if (gp > b->max_pages) gp = b->max_pages;
-        if (b->exec && b->graph_pages != gp) {
-            (void)hipGraphExecDestroy(b->exec);
-            (void)hipGraphDestroy(b->graph);
-            b->exec = nullptr;
-            b->graph = nullptr;
+        if (r.exec && (r.graph_pages != gp || r.graph_launches != launches)) {
+            (void)hipGraphExecDestroy(r.exec);
+            (void)hipGraphDestroy(r.graph);
+            r.exec = nullptr;
+            r.graph = nullptr;
         }
-        if (!b->exec) {
+        if (!r.exec) {
             hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return fail(e);
-            rc = record(b, table_size(gp), b->cap_stream);
+            rc = record(b, r, table_size(gp), launches, b->cap_stream);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->cap_stream, &g);
             if (rc) {
@@ -363,25 +461,27 @@ int binarize_batch_run(bz_batch *b, const bz_page *pages, int n_pages, int use_g
                 return rc;
             }
             if (e != hipSuccess) return fail(e);
-            b->graph = g;
-            if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return fail(e);
-            b->graph_pages = gp;
+            r.graph = g;
+            if ((e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0)) != hipSuccess) return fail(e);
+            r.graph_pages = gp;
+            r.graph_launches = launches;
         }
-        hipError_t e = hipGraphLaunch(b->exec, st);
+        hipError_t e = hipGraphLaunch(r.exec, st);
         if (e != hipSuccess) return fail(e);
     } else {
-        rc = record(b, table_size(n_pages), st);
+        rc = record(b, r, table_size(n_pages), launches, st);
         if (rc) return rc;
     }
-    hipError_t e = hipEventRecord(b->done, st);
+    hipError_t e = hipEventRecord(r.done, st);
     if (e != hipSuccess) return fail(e);
-    b->pending = true;
+    r.pending = true;
+    b->cur ^= 1;
     return BZ_OK;
 }
 
 int binarize_batch_info(const bz_batch *b, int *grid, int *lds_cap, int *last_items) {
     if (!b) return BZ_ERR_NULL;
-    if (grid) *grid = b->grid;
+    if (grid) *grid = b->grid[0];  // 256-column ring pages at four workgroups per CU
     if (lds_cap) *lds_cap = b->lds_cap;
     if (last_items) *last_items = b->last_items;
     return BZ_OK;
@@ -391,14 +491,13 @@ int binarize_batch_info(const bz_batch *b, int *grid, int *lds_cap, int *last_it
 
 namespace {
 
-// Batch objects behind the one-call binarize_batch: two per device, used in
-// turn, so a call waits on the host only for the run before the previous
-// one (whose pinned table it rewrites).  They grow to the largest call seen
-// and live until the process ends.
+// The batch object behind the one-call binarize_batch, one per device: its
+// two sets of run buffers let a call wait on the host only for the run
+// before the previous one.  It grows to the largest call seen and lives
+// until the process ends.
 struct OneCallPool {
     std::mutex mu;
-    bz_batch *obj[2] = {nullptr, nullptr};
-    int next = 0;
+    bz_batch *obj = nullptr;
 };
 OneCallPool g_pools[kMaxDevices];
 
@@ -415,9 +514,9 @@ int binarize_batch(const bz_page *pages, int n_pages, void *stream) {
     if (dev < 0 || dev >= kMaxDevices) return fail(hipErrorInvalidDevice);
     OneCallPool &pool = g_pools[dev];
     std::lock_guard<std::mutex> lock(pool.mu);
-    bz_batch *&b = pool.obj[pool.next];
+    bz_batch *&b = pool.obj;
     if (!b || b->max_pages < n_pages) {
-        if (b) binarize_batch_destroy(b);  // waits for its last run
+        if (b) binarize_batch_destroy(b);  // waits for its last runs
         b = nullptr;
         int cap = 64;
         while (cap < n_pages) cap *= 2;
@@ -427,20 +526,21 @@ int binarize_batch(const bz_page *pages, int n_pages, void *stream) {
             return rc;
         }
     }
-    pool.next ^= 1;
     return binarize_batch_run(b, pages, n_pages, 0, stream);
 }
 
 void binarize_batch_destroy(bz_batch *b) {
     if (!b) return;
-    if (b->pending) (void)hipEventSynchronize(b->done);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->done) (void)hipEventDestroy(b->done);
+    for (RunBuffers &r : b->buf) {
+        if (r.pending) (void)hipEventSynchronize(r.done);
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        if (r.done) (void)hipEventDestroy(r.done);
+        if (r.counter) (void)hipFree(r.counter);
+        if (r.dev_table) (void)hipFree(r.dev_table);
+        if (r.host_table) (void)hipHostFree(r.host_table);
+    }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    if (b->counter) (void)hipFree(b->counter);
-    if (b->dev_table) (void)hipFree(b->dev_table);
-    if (b->host_table) (void)hipHostFree(b->host_table);
     delete[] b->spans;
     delete[] b->span_max;
     delete[] b->descs;

@@ -97,8 +97,8 @@ BZ_HD inline int rows_bytes(int rows, int tile_w, int win) { return round_up(row
 // ring would allow fewer than four workgroups per CU (the occupancy of the
 // narrow windows): staging three blocks costs more than staging one row set,
 // so the ring is kept where it does not limit occupancy.  Both layouts give
-// identical bytes.  The batched launch keeps the ring for every page (its
-// one kernel holds every tile variant; `allow_blocks` false).
+// identical bytes.  `allow_blocks` false keeps the ring (a single-page
+// launch with few tiles; a ring page of the batched launch).
 constexpr int kGrayBlocks = 3;
 constexpr int kStartRows = 4 * kRowsPerStep;
 BZ_HD inline int ring_layout_lds(int tile_w, int win) { return rows_bytes(ring_depth(win), tile_w, win) + v_bytes(tile_w, win); }

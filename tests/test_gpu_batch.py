@@ -100,13 +100,94 @@ def test_config2_rgb_pages_batched(bz):
         assert np.array_equal(out, single(bz, img, win, k, R, rule))
 
 
+def blocks_jobs(seed):
+    """Pages for a batch whose LDS cap (40896 B, four workgroups per CU) is
+    below the ring of the wider windows: gray pages at win 61-241 take the
+    256-column blocks layout and win 255 the 128-column one (both rules, so
+    every blocks group), gray win 15 / 31 and RGB pages the ring; ragged sizes
+    of one to several tiles."""
+    import pagegen
+    rng = np.random.default_rng(seed)
+    spec = [(1, 61, 0), (1, 101, 1), (1, 151, 0), (1, 241, 1), (1, 255, 0), (1, 255, 1), (1, 15, 0),
+            (3, 31, 1), (3, 61, 0), (1, 31, 1), (1, 101, 0)]
+    jobs = []
+    for i, (C, win, rule) in enumerate(spec):
+        H, W = int(rng.integers(40, 700)), int(rng.integers(40, 900))
+        k = f32(float(rng.uniform(-0.3, 0.6)))
+        img = pagegen.page(H, W, max(1, pagegen.strokes_for(H, W)), seed=seed * 100 + i, channels=C)
+        jobs.append((img, win, k, 128.0, rule))
+    return jobs
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_blocks_layout_pages_in_a_small_cap_batch(bz, oracle_mod, use_graph):
+    """With an LDS cap of a quarter CU, gray pages whose ring does not fit run
+    in the blocks layout (one kernel per blocks tile variant, after the ring
+    kernel): every page's bytes equal the single-page entry point's, and the
+    oracle's where it finishes quickly."""
+    from oracle.compare import compare_out
+    jobs = blocks_jobs(31)
+    with bz.Batch(16, lds_cap=40896) as B:
+        outs = run_batch(bz, B, jobs, use_graph)
+        # four workgroups per CU at this cap
+        assert B.info()["grid"] == 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    for (img, win, k, R, rule), out in zip(jobs, outs):
+        assert np.array_equal(out, single(bz, img, win, k, R, rule)), (img.shape, win, rule)
+        if img.shape[0] * img.shape[1] * min(win, img.shape[0]) * min(win, img.shape[1]) < 3e8:
+            ref = oracle_mod.binarize(img, win, k, R, rule)
+            assert compare_out(out, ref.out, ref.gray, ref.t)["ok"], (img.shape, win, rule)
+
+
+def test_graph_recaptures_when_the_kernel_groups_change(bz):
+    """Graph mode on one batch object: a batch with blocks pages, then one
+    with ring pages only (fewer kernels in the graph), then the first again;
+    each replayed twice and checked."""
+    a = blocks_jobs(41)
+    b = [j for j in blocks_jobs(42) if j[1] <= 31 or j[0].ndim == 3]
+    expect = {id(j): single(bz, *j) for j in a + b}
+    with bz.Batch(16, lds_cap=40896) as B:
+        for jobs in (a, b, a):
+            for _ in range(2):
+                outs = run_batch(bz, B, jobs, use_graph=True)
+                for j, o in zip(jobs, outs):
+                    assert np.array_equal(expect[id(j)], o), (j[0].shape, j[1])
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_back_to_back_runs_on_two_streams(bz, use_graph):
+    """One batch object, five runs enqueued without waiting, alternating
+    between two streams: each run uses the object's other set of run
+    buffers, and the third waits for the first before reusing its set; every
+    run's pages must come out as when binarized alone."""
+    sets = [mixed_jobs(50 + i, 6, max_side=500) for i in range(5)]
+    expect = [[single(bz, *j) for j in jobs] for jobs in sets]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev = []
+    for jobs in sets:
+        d = []
+        for img, win, k, R, rule in jobs:
+            t = torch.from_numpy(img).cuda()
+            d.append((t, torch.full(img.shape[:2], 7, dtype=torch.uint8, device="cuda"), win, k, R, rule))
+        dev.append(d)
+    torch.cuda.synchronize()
+    with bz.Batch(16) as B:
+        for i, d in enumerate(dev):
+            B.run(d, use_graph=use_graph, stream=streams[i % 2])
+        torch.cuda.synchronize()
+    for i, (d, e) in enumerate(zip(dev, expect)):
+        for j, (job, ref) in enumerate(zip(d, e)):
+            assert np.array_equal(job[1].cpu().numpy(), ref), (i, j)
+
+
 def test_batch_rejects_bad_pages(bz):
     img = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
     out = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    rgb = torch.zeros((64, 64, 3), dtype=torch.uint8, device="cuda")
     with bz.Batch(2, lds_cap=48 * 1024) as B:
         with pytest.raises(bz.BinarizeError) as ei:
-            B.run([(img, out, 255, 0.5, 128.0, 0)])  # needs more LDS than the cap
+            B.run([(rgb, out, 255, 0.5, 128.0, 0)])  # an RGB ring that needs more LDS than the cap
         assert ei.value.code == -9
+        B.run([(img, out, 255, 0.5, 128.0, 0)])  # a gray page of that window fits in the blocks layout
         with pytest.raises(bz.BinarizeError) as ei:
             B.run([(img, out, 0, 0.5, 128.0, 0)])
         assert ei.value.code == -4

@@ -356,23 +356,27 @@ def test_blocks_layout_pages(bz, oracle_mod, page4096, H, W, win, rule, k):
     """Gray pages with wide windows and more tiles than the win + 8-row ring
     runs at once take the three-block layout of the input rows (aligned and
     unaligned bodies: W = 2051 is not a multiple of 16).  Every pixel against
-    the oracle, and bit-identical to the batched launch, which keeps the ring
-    layout for every page."""
+    the oracle; bit-identical to the ring layout (forced by one 4096-row tile
+    per tile column: fewer tiles than the ring runs at once), to the batched
+    launch (its blocks-layout kernel, 128-row tiles) and to a row-strided
+    view."""
     from oracle.compare import compare_out
     k = f32(k)
     img = np.ascontiguousarray(page4096[:H, :W])
     print(f"blocks layout: {H}x{W} win {win} rule {rule} k {k}", flush=True)
     timg = torch.from_numpy(img).cuda()
     out = bz.binarize(timg, win, k, 128.0, rule)
-    ring = torch.empty_like(out)
-    bz.batch([(timg, ring, win, k, 128.0, rule)])
+    ring = bz.binarize(timg, win, k, 128.0, rule, tile=(256, 4096))
+    batched = torch.empty_like(out)
+    bz.batch([(timg, batched, win, k, 128.0, rule)])
     torch.cuda.synchronize()
     # the same page as a row-strided view of the whole 4096-wide page
     full = torch.from_numpy(page4096).cuda()
     strided = bz.binarize(full[:H, :W], win, k, 128.0, rule)
     torch.cuda.synchronize()
-    out, ring, strided = out.cpu().numpy(), ring.cpu().numpy(), strided.cpu().numpy()
+    out, ring, batched, strided = (t.cpu().numpy() for t in (out, ring, batched, strided))
     assert np.array_equal(out, ring)
+    assert np.array_equal(out, batched)
     assert np.array_equal(out, strided)
     ref = oracle_mod.binarize(img, win, k, 128.0, rule)
     rep = compare_out(out, ref.out, ref.gray, ref.t)
