@@ -50,7 +50,8 @@ struct PageArgs {
     int n_tiles;      // tiles_x * tiles_y
     int rp;           // LDS ring row pitch in bytes (multiple of 16)
     int depth;        // ring depth in rows
-    int row_aligned;  // input rows 16-byte aligned and a multiple of 16 pixels, output rows 8-byte aligned
+    int row_aligned;  // input rows 16-byte aligned and a multiple of 16 pixels, output rows 8-byte
+                      // aligned, both pitches below 2^28
     int blocks;       // gray page in the blocks layout (see gray_blocks)
 };
 

@@ -96,6 +96,28 @@ __device__ __forceinline__ void put_out_byte(uint32_t &w, int b, bool dark, uint
 }
 #undef BZ_PUT_BYTE
 
+// LDS-typed views, so that offsets into the tile's LDS stay 32-bit (plain
+// vector types: the HIP vector classes have no address-space-qualified
+// assignment).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) u32x2 lds_v2;
+typedef __attribute__((address_space(3))) u32x4 lds_v4;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(1))) uint8_t glb_u8;
+
+// A pointer whose value is the same on every lane, kept in scalar registers:
+// reading it through readfirstlane stops the compiler from folding
+// per-thread offsets into it (which would turn a scalar base plus a 32-bit
+// offset back into a 64-bit per-thread address).
+__device__ __forceinline__ glb_u8 *uniform_global(uint8_t *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (glb_u8 *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------- staging
 //
 // A staging job is 16 consecutive pixels of one image row.  Its raw bytes are
@@ -191,15 +213,62 @@ struct Stager {
     RawChunk<C> k;
     int job_row, job_q;  // job_row >= kRowsPerStep: this thread has no job
     bool in_image;
+    // INT bodies: the job's byte offsets from the first row of its block
+    // and from its row (32-bit offsets: pitches are below 2^28 there), and
+    // whether its chunk lies inside the image's columns; cols_in: every
+    // chunk of the tile does.
+    uint32_t voff, xoff;
+    bool col_in, cols_in;
+    bool zero_free;  // the last fetch staged rows and chunks all inside the image
 
-    __device__ __forceinline__ void init(const PageArgs &a) {
+    __device__ __forceinline__ void init(const PageArgs &a, int xr0) {
         const int nq = a.rp >> 4;
         job_row = (int)threadIdx.x / nq;
         job_q = (int)threadIdx.x - job_row * nq;
         in_image = true;
+        zero_free = false;
+        if (INT) {
+            const int xs = xr0 + 16 * job_q;
+            col_in = xs >= 0 && xs < a.W;
+            cols_in = xr0 >= 0 && xr0 + a.rp <= a.W;
+            xoff = (uint32_t)(C * min(max(xs, 0), a.W - 16));
+            voff = (uint32_t)job_row * (uint32_t)a.pitch_in + xoff;
+        }
     }
 
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
+        if (INT) {
+            // Every job loads from one uniform row address, that of the
+            // block's first row clamped into the image, plus a 32-bit offset:
+            // fixed when every row of the block lies inside the image (the
+            // usual case), else from the job's own clamped row.
+            const bool inside = row0 >= 0 && row0 + nrows <= a.H;  // uniform
+            const int rb = min(max(row0, 0), a.H - 1);
+            uint32_t off = voff;
+            in_image = col_in;
+            if (!inside) {
+                const int row = row0 + job_row;
+                const int rc = min(max(row, 0), a.H - 1);
+                off = (uint32_t)(rc - rb) * (uint32_t)a.pitch_in + xoff;
+                in_image = col_in && row >= 0 && row < a.H;
+            }
+            zero_free = inside && cols_in;
+            if (job_row < nrows) {
+                const uint8_t *blk = a.img + (size_t)rb * (size_t)a.pitch_in;  // uniform
+                const uint4 *q = reinterpret_cast<const uint4 *>(blk + off);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const uint4 v = q[i];
+                    k.w[4 * i] = v.x;
+                    k.w[4 * i + 1] = v.y;
+                    k.w[4 * i + 2] = v.z;
+                    k.w[4 * i + 3] = v.w;
+                }
+                k.sh = 0;
+            }
+            return;
+        }
+        zero_free = false;
         if (job_row < nrows) {
             const int row = row0 + job_row;
             int xs = xr0 + 16 * job_q;
@@ -214,12 +283,25 @@ struct Stager {
     }
 
     // Store into rows `rows`, `rows` + rp, ... (no ring wrap).
+    // Store the fetched chunk as 16 gray levels at `p`, zero outside the
+    // image.  Chunks outside are rare (edge tiles, rows beyond the image):
+    // they are overwritten with zeros behind the uniform zero_free test, which
+    // the empty volatile asm keeps a branch (as selects, the masking would
+    // run on every step).
+    template <class P>
+    __device__ __forceinline__ void put(const PageArgs &a, P *p, int xr0, bool clamp) const {
+        const uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
+        *p = u32x4{v.x, v.y, v.z, v.w};
+        if (!zero_free) {
+            asm volatile("");
+            if (!in_image) *p = u32x4{0u, 0u, 0u, 0u};
+        }
+    }
+
     __device__ __forceinline__ void store_rows(const PageArgs &a, uint8_t *rows, int nrows, int xr0,
                                                bool clamp) const {
         if (job_row >= nrows) return;
-        uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
-        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
-        *(uint4 *)(rows + job_row * a.rp + 16 * job_q) = v;
+        put(a, (u32x4 *)(rows + job_row * a.rp + 16 * job_q), xr0, clamp);
     }
 
     __device__ __forceinline__ void store(const PageArgs &a, uint8_t *ring, int slot0, int nrows, int xr0,
@@ -227,9 +309,14 @@ struct Stager {
         if (job_row >= nrows) return;
         int sl = slot0 + job_row;
         if (sl >= a.depth) sl -= a.depth;
-        uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
-        if (!in_image) v = make_uint4(0u, 0u, 0u, 0u);
-        *(uint4 *)(ring + sl * a.rp + 16 * job_q) = v;
+        put(a, (u32x4 *)(ring + sl * a.rp + 16 * job_q), xr0, clamp);
+    }
+
+    // Store at byte `off` of the tile's LDS (the job's own slot and chunk).
+    __device__ __forceinline__ void store_at(const PageArgs &a, lds_u8 *lds, uint32_t off, int nrows, int xr0,
+                                             bool clamp) const {
+        if (job_row >= nrows) return;
+        put(a, (lds_v4 *)(lds + off), xr0, clamp);
     }
 };
 
@@ -313,11 +400,29 @@ __device__ __forceinline__ float threshold_value(const PageArgs &a, uint32_t S1,
     return (float)(RULE == 0 ? m * __builtin_fma(a.c2, s, a.c1) : __builtin_fma((double)a.k, s, m));
 }
 
+// sqrt(D) in fp32 for a whole window (n = win^2), with S2 = b2 + e2 given
+// as nb2 = n b2 (an exact fp64 product, shared by a thread's outputs) and
+// e2 = S2 - b2 (|e2| < 2^27): D = n e2 + (n b2 - S1^2), each step exact (all
+// terms are integers below 2^49), so D equals n S2 - S1^2 bit for bit.
+__device__ __forceinline__ float exact_sqrt_d_whole(double nd, double nb2, uint32_t S1, int32_t e2, double &s1d) {
+    s1d = (double)S1;
+    const double D = __builtin_fma(nd, (double)e2, __builtin_fma(-s1d, s1d, nb2));
+    return __builtin_amdgcn_sqrtf((float)D);
+}
+
 // Whole-window Sauvola (per-page constants): true if f < t (output 0).
 __device__ __forceinline__ bool dark_sauvola_full(const WholeWindow &q, uint32_t f, uint32_t S1, uint32_t S2,
                                                   float &sq) {
     double s1d;
     sq = exact_sqrt_d(q.nd, S1, S2, s1d);
+    return (double)f < s1d * __builtin_fma(q.c2n2, (double)sq, q.c1n);
+}
+
+// The same with S2 given as for exact_sqrt_d_whole (identical D and result).
+__device__ __forceinline__ bool dark_sauvola_full(const WholeWindow &q, uint32_t f, uint32_t S1, double nb2,
+                                                  int32_t e2, float &sq) {
+    double s1d;
+    sq = exact_sqrt_d_whole(q.nd, nb2, S1, e2, s1d);
     return (double)f < s1d * __builtin_fma(q.c2n2, (double)sq, q.c1n);
 }
 
@@ -338,6 +443,14 @@ __device__ __forceinline__ bool dark_niblack(const PageArgs &a, uint32_t f, uint
     return (float)((int)__umul24(n, f) - (int)S1) < a.k * sq;
 }
 
+// Whole-window Niblack (n = win^2), S2 given as for exact_sqrt_d_whole.
+__device__ __forceinline__ bool dark_niblack_full(const PageArgs &a, const WholeWindow &q, uint32_t n, uint32_t f,
+                                                 uint32_t S1, double nb2, int32_t e2, float &sq) {
+    double s1d;
+    sq = exact_sqrt_d_whole(q.nd, nb2, S1, e2, s1d);
+    return (float)((int)__umul24(n, f) - (int)S1) < a.k * sq;
+}
+
 // ---------------------------------------------------------------- output
 
 // Output bytes are written once and never read back by the kernel: their
@@ -345,13 +458,21 @@ __device__ __forceinline__ bool dark_niblack(const PageArgs &a, uint32_t f, uint
 // data rather than keeping them resident next to the input rows that
 // neighbouring tiles read again.
 __device__ __forceinline__ void store_nt8(uint8_t *p, uint32_t lo, uint32_t hi) {
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 v = {lo, hi};
     __builtin_nontemporal_store(v, (u32x2 *)p);
 }
 
 __device__ __forceinline__ void store_nt4(uint8_t *p, uint32_t w) {
     __builtin_nontemporal_store(w, (uint32_t *)p);
+}
+
+__device__ __forceinline__ void store_nt8(glb_u8 *p, uint32_t lo, uint32_t hi) {
+    const u32x2 v = {lo, hi};
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) u32x2 *)p);
+}
+
+__device__ __forceinline__ void store_nt4(glb_u8 *p, uint32_t w) {
+    __builtin_nontemporal_store(w, (__attribute__((address_space(1))) uint32_t *)p);
 }
 
 // Store OPT output bytes (packed little-endian in w) at columns [xs, xs+OPT)
@@ -520,15 +641,15 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // entering rows (and in the blocks layout the leaving and centre rows
     // too).
     Stager<C, INT> pre, pre_l, pre_c;
-    pre.init(a);
+    pre.init(a, xr0);
     if (blocks) {
-        pre_l.init(a);
-        pre_c.init(a);
+        pre_l.init(a, xr0);
+        pre_c.init(a, xr0);
         // Rounds of kStartRows rows staged into the whole LDS and summed.
         constexpr int NS = kStartRows / RB;
         Stager<C, INT> st[NS];
 #pragma unroll
-        for (int u = 0; u < NS; ++u) st[u].init(a);
+        for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
         for (int r0 = 0; r0 < win; r0 += kStartRows) {
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
@@ -567,7 +688,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
         Stager<C, INT> st[NS];
 #pragma unroll
-        for (int u = 0; u < NS; ++u) st[u].init(a);
+        for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
         for (int r0 = 0; r0 < win; r0 += NS * RB) {
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
@@ -606,6 +727,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
+    // INT bodies: this thread's output bytes relative to the step's first
+    // output row (pitches are below 2^28 there)
+    const uint32_t out_off = (uint32_t)hr * (uint32_t)a.pitch_out + (uint32_t)(X0 + hs * OPT);
     // Steps whose windows all span win rows, in a 256-column block of the
     // page (counted from column 0) whose windows all span win columns, are
     // decided with the per-tile Sauvola constants; every other pixel takes
@@ -624,8 +748,21 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // y0 + hi), first leaving row (y0 - lo - 1) and first output row (y0),
     // advanced by RB per step; slot 0 holds image row base = Y0 - lo - 1 and
     // depth > win.
-    int s_in = win, s_out = 0, s_ctr = lo + 1;
+    int s_in = win, s_out = 0;
     const int ring_len = depth * rp;  // bytes of the ring
+    lds_u8 *const lds = (lds_u8 *)smem;
+    // Per-thread LDS byte offsets, advanced by RB rows per step with one
+    // wrap test (a row plus a column below rp: at or past ring_len means
+    // the row wrapped): this thread's staging chunk in the slots of the next
+    // step's entering rows, and its window centres (in the blocks layout, a
+    // fixed row of the centre block).
+    auto wrap_row = [&](int r) { return r >= depth ? r - depth : r; };
+    uint32_t st_off = (uint32_t)(wrap_row(win + RB + pre.job_row) * rp + 16 * pre.job_q);
+    uint32_t ctr_off = (uint32_t)((blocks ? 2 * RB + hr : wrap_row(lo + 1 + hr)) * rp + off0 + lo + hs * OPT);
+    auto advance = [&](uint32_t &off) {
+        off += (uint32_t)(RB * rp);
+        if (off >= (uint32_t)ring_len) off -= (uint32_t)ring_len;
+    };
     __syncthreads();
 
     for (int y0 = Y0; y0 < Yend; y0 += RB) {
@@ -720,20 +857,17 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const uint32_t b2 = half_total(h2i) + s2i - a2;
 
         __builtin_amdgcn_s_setprio(0);  // the decisions: fill-in work
-        // gray levels of the output row (centre of the window)
-        int sy = blocks ? 2 * RB + hr : s_ctr + hr;  // LDS row of this output row
-        if (!blocks && sy >= depth) sy -= depth;
+        // gray levels of the output row (centre of the window), at ctr_off.
         // (X0 is a multiple of 16 and xr0 = X0 - ceil16(lo + 1), so the
         // window centre of column X0 sits at LDS column off0 + lo =
         // ceil16(lo + 1) and each thread's OPT bytes are OPT-aligned.)
-        const int fo = sy * rp + off0 + lo + hs * OPT;
         uint32_t fw[OPT / 4];
         if (OPT == 8) {
-            const uint2 q = *(const uint2 *)(smem + fo);
+            const u32x2 q = *(const lds_v2 *)(lds + ctr_off);
             fw[0] = q.x;
             fw[OPT / 4 - 1] = q.y;
         } else {
-            fw[0] = *(const uint32_t *)(smem + fo);
+            fw[0] = *(const lds_u32 *)(lds + ctr_off);
         }
 
         // every window of the step's rows has win rows (uniform per step)
@@ -746,16 +880,19 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         const uint32_t kFF = __builtin_amdgcn_readfirstlane(0xffu), kZero = 0u;
         float sqv[OPT];
         if (x_inside && full_rows) {  // uniform: every window of the step and block is win x win
+            const double nb2 = q_full.nd * (double)b2;  // exact: below 2^48
             if (RULE == 0) {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const bool dark = dark_sauvola_full(q_full, byte_at(fw, j), b1 + E1[j], b2 + E2[j], sqv[j]);
+                    const bool dark = dark_sauvola_full(q_full, byte_at(fw, j), b1 + E1[j], nb2, (int32_t)E2[j],
+                                                        sqv[j]);
                     put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < OPT; ++j) {
-                    const bool dark = dark_niblack(a, byte_at(fw, j), b1 + E1[j], b2 + E2[j], n_full, sqv[j]);
+                    const bool dark = dark_niblack_full(a, q_full, n_full, byte_at(fw, j), b1 + E1[j], nb2,
+                                                        (int32_t)E2[j], sqv[j]);
                     put_out_byte(ow[j >> 2], j & 3, dark, kFF, kZero);
                 }
             }
@@ -790,17 +927,19 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
             }
         } else {
             s_in = s_in + RB >= depth ? s_in + RB - depth : s_in + RB;
+            advance(ctr_off);
             s_out = s_out + RB >= depth ? s_out + RB - depth : s_out + RB;
-            s_ctr = s_ctr + RB >= depth ? s_ctr + RB - depth : s_ctr + RB;
             if (y0 + RB < Yend) {
-                pre.store(a, ring, s_in, RB, xr0, clamp);
+                pre.store_at(a, lds, st_off, RB, xr0, clamp);
+                advance(st_off);
                 if (y0 + 2 * RB < Yend) pre.fetch(a, y0 + 2 * RB + hi, RB, xr0, clamp);
             }
         }
         if (y < Yend) {
             if (INT) {  // W is a multiple of 16: the thread's outputs lie wholly inside or outside
                 if (xs < a.W) {
-                    uint8_t *p = a.out + (size_t)y * (size_t)a.pitch_out + xs;
+                    // the step's first output row (uniform) plus a fixed 32-bit offset
+                    glb_u8 *p = uniform_global(a.out + (size_t)y0 * (size_t)a.pitch_out) + out_off;
                     if (OPT == 8)
                         store_nt8(p, ow[0], ow[OPT / 4 - 1]);
                     else
