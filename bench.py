@@ -166,6 +166,9 @@ def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) 
     stream = torch.cuda.current_stream(dev)
 
     def timed(fn):
+        # back-to-back calls: each call's host work (marshalling and
+        # planning the pages) overlaps the GPU's work on the previous one;
+        # only the first call's host work falls inside the timed span
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -290,95 +293,6 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
-
-
-def gpu_pci_slot(dev: int = 0) -> str | None:
-    """PCI slot name ("0000:xx:yy.z") of a HIP device, from the HIP runtime."""
-    import ctypes
-    try:
-        hip = ctypes.CDLL("libamdhip64.so")
-        buf = ctypes.create_string_buffer(64)
-        if hip.hipDeviceGetPCIBusId(buf, 64, dev) != 0:
-            return None
-        return buf.value.decode().lower()
-    except OSError:
-        return None
-
-
-def gpu_sclk_mhz(slot: str | None) -> list:
-    """Current shader clock (MHz) of the GPU at PCI slot `slot`, from the
-    amdgpu power-state table in sysfs (the level marked '*'); empty when it
-    cannot be read or the card is not found (the host may list GPUs this
-    process does not use)."""
-    import glob
-    import re
-    if not slot:
-        return []
-    out = []
-    for card in sorted(glob.glob("/sys/class/drm/card*/device")):
-        try:
-            with open(card + "/uevent") as fh:
-                if f"PCI_SLOT_NAME={slot}" not in fh.read().lower():
-                    continue
-            with open(card + "/pp_dpm_sclk") as fh:
-                for line in fh:
-                    if line.rstrip().endswith("*"):
-                        m = re.search(r"(\d+)\s*Mhz", line, re.IGNORECASE)
-                        if m:
-                            out.append(int(m.group(1)))
-        except OSError:
-            continue
-    return out
-
-
-def sample_sclk_under_load(launch, dev, seconds: float = 0.4) -> dict:
-    """Shader clock while the GPU runs the bench's own launches: an untimed
-    burst of the five cases (about `seconds` long, after the timed region)
-    with a host thread reading sysfs meanwhile.  The timed region itself is
-    too short for the sysfs reads, which take milliseconds each."""
-    import threading
-
-    import torch
-    slot = gpu_pci_slot(dev.index or 0)
-    clk, stop = [], threading.Event()
-
-    def sample():
-        while not stop.is_set():
-            clk.extend(gpu_sclk_mhz(slot))
-            time.sleep(0.002)
-
-    th = threading.Thread(target=sample, daemon=True)
-    t0 = time.perf_counter()
-    th.start()
-    while time.perf_counter() - t0 < seconds:
-        for _ in range(40):
-            for c in CASES:
-                launch(c)
-        torch.cuda.synchronize()
-    stop.set()
-    th.join()
-    rec = {"pci_slot": slot, "samples": len(clk), "median_mhz": float(np.median(clk)) if clk else None,
-           "min_mhz": min(clk) if clk else None, "max_mhz": max(clk) if clk else None,
-           "when": "untimed burst of the bench launches right after the timed region"}
-    if not clk:  # say why: the GPUs whose sysfs entries this process sees
-        rec["sysfs_slots_seen"] = sysfs_gpu_slots()
-    return rec
-
-
-def sysfs_gpu_slots() -> list:
-    """PCI slots of the GPUs listed under /sys/class/drm, with whether their
-    power-state table can be read."""
-    import glob
-    seen = []
-    for card in sorted(glob.glob("/sys/class/drm/card*/device")):
-        try:
-            with open(card + "/uevent") as fh:
-                ps = [x.split("=", 1)[1] for x in fh.read().split() if x.startswith("PCI_SLOT_NAME=")]
-        except OSError:
-            continue
-        readable = os.access(card + "/pp_dpm_sclk", os.R_OK)
-        seen += [f"{p}{'' if readable else ' (no pp_dpm_sclk)'}" for p in ps]
-    return seen
 
 
 def run_oracle_single_thread_cfg0() -> dict:
@@ -632,7 +546,7 @@ def main() -> int:
         print(json.dumps(run_otsu_workload(max(10, args.steps), args.pool_mb)), flush=True)
         return 0
     if args.workload != "page4096":
-        print(json.dumps(run_batch_workload(args.workload, max(1, args.steps // 20), args.lds_cap,
+        print(json.dumps(run_batch_workload(args.workload, max(12, args.steps // 20), args.lds_cap,
                                             args.batch_tile_h)), flush=True)
         return 0
 
@@ -677,7 +591,6 @@ def main() -> int:
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    sclk = sample_sclk_under_load(launch, dev)
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
@@ -740,7 +653,6 @@ def main() -> int:
         "cases": cases,
         "copy_GBps": copy_gbps,
         "copy_stream_GBps": copy_stream_gbps,
-        "gpu_sclk_under_load": sclk,
         "wall_s": t_wall,
     }
     # which roof limits the dominant kernel: the instruction-issue (VALU)
@@ -756,8 +668,8 @@ def main() -> int:
         extras["latency_cfg0"] = run_latency_cfg0()
         # batches at the default LDS cap (each launch of a batch takes the
         # occupancy its pages' tiles allow) and 256-row tiles
-        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 5, 0, 256))
-        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 3, 0, 256))
+        extras["batch_a4_rgb_64"] = compact_batch(run_batch_workload("batch-rgb", 12, 0, 256))
+        extras["batch_uneven_512"] = compact_batch(run_batch_workload("batch-mixed", 12, 0, 256))
         torch.cuda.empty_cache()
         extras["serve"] = compact_serve(run_serve_workload([200.0, 1000.0, 5000.0], 1.0, 4, 32, "both"))
         torch.cuda.empty_cache()
