@@ -111,11 +111,12 @@ BZ_HD inline int ring_rows(int tile_w, int win, int channels, bool allow_blocks 
 }
 // LDS layout: rows (ring or blocks) | Va1 [RB][va_pitch] u16 |
 // Vb1 [RB][vb_pitch] u16 | Va2 [RB][va_pitch] u32 | Vb2 [RB][vb_pitch] u32,
-// and in the blocks layout at least kStartRows rows of the row pitch.
+// and in the blocks layout at least 2 kStartRows rows of the row pitch (the
+// start-up's two staging halves).
 BZ_HD inline int tile_lds_bytes(int tile_w, int win, int channels, bool allow_blocks = true) {
     if (!gray_blocks(tile_w, win, channels, allow_blocks)) return ring_layout_lds(tile_w, win);
     const int b = rows_bytes(kGrayBlocks * kRowsPerStep, tile_w, win) + v_bytes(tile_w, win);
-    const int s = rows_bytes(kStartRows, tile_w, win);
+    const int s = rows_bytes(2 * kStartRows, tile_w, win);
     return b > s ? b : s;
 }
 

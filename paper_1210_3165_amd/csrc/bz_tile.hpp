@@ -645,12 +645,17 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     if (blocks) {
         pre_l.init(a, xr0);
         pre_c.init(a, xr0);
-        // Rounds of kStartRows rows staged into the whole LDS and summed.
+        // Rounds of kStartRows rows staged and summed, in the two halves of
+        // a 2 kStartRows-row area at the start of the tile's LDS in turn: a
+        // round stores into the half that was summed two rounds before,
+        // which every wave has finished with once it has passed the previous
+        // round's barrier, so one barrier per round suffices.
         constexpr int NS = kStartRows / RB;
         Stager<C, INT> st[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
-        for (int r0 = 0; r0 < win; r0 += kStartRows) {
+        for (int r0 = 0, half = 0; r0 < win; r0 += kStartRows, half ^= 1) {
+            uint8_t *const rows = smem + half * kStartRows * rp;
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
                 const int rr = r0 + u * RB;
@@ -661,14 +666,13 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                 pre_l.fetch(a, base, RB, xr0, clamp);
                 pre_c.fetch(a, Y0, RB, xr0, clamp);
             }
-            if (r0 > 0) __syncthreads();  // the previous round is summed
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
                 const int rr = r0 + u * RB;
-                if (rr < win) st[u].store_rows(a, smem + u * RB * rp, min(RB, win - rr), xr0, clamp);
+                if (rr < win) st[u].store_rows(a, rows + u * RB * rp, min(RB, win - rr), xr0, clamp);
             }
             __syncthreads();
-            add_rows(smem, min(kStartRows, win - r0));
+            add_rows(rows, min(kStartRows, win - r0));
         }
         __syncthreads();  // start-up rows summed: the blocks may be written
         pre.store_rows(a, blkE, RB, xr0, clamp);
