@@ -649,28 +649,36 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // a 2 kStartRows-row area at the start of the tile's LDS in turn: a
         // round stores into the half that was summed two rounds before,
         // which every wave has finished with once it has passed the previous
-        // round's barrier, so one barrier per round suffices.
+        // round's barrier, so one barrier per round suffices.  The next
+        // round's loads are issued as soon as this round's rows are stored,
+        // so they are in flight across the barrier and the summing.
         constexpr int NS = kStartRows / RB;
         Stager<C, INT> st[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
+        // loads of the rounds starting at r (with the first step's blocks
+        // alongside the last round's)
+        auto fetch_round = [&](int r) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                const int rr = r + u * RB;
+                if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
+            }
+            if (r + kStartRows >= win) {
+                pre.fetch(a, Y0 + hi, RB, xr0, clamp);
+                pre_l.fetch(a, base, RB, xr0, clamp);
+                pre_c.fetch(a, Y0, RB, xr0, clamp);
+            }
+        };
+        fetch_round(0);
         for (int r0 = 0, half = 0; r0 < win; r0 += kStartRows, half ^= 1) {
             uint8_t *const rows = smem + half * kStartRows * rp;
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
                 const int rr = r0 + u * RB;
-                if (rr < win) st[u].fetch(a, base + rr, min(RB, win - rr), xr0, clamp);
-            }
-            if (r0 + kStartRows >= win) {  // the first step's blocks
-                pre.fetch(a, Y0 + hi, RB, xr0, clamp);
-                pre_l.fetch(a, base, RB, xr0, clamp);
-                pre_c.fetch(a, Y0, RB, xr0, clamp);
-            }
-#pragma unroll
-            for (int u = 0; u < NS; ++u) {
-                const int rr = r0 + u * RB;
                 if (rr < win) st[u].store_rows(a, rows + u * RB * rp, min(RB, win - rr), xr0, clamp);
             }
+            if (r0 + kStartRows < win) fetch_round(r0 + kStartRows);
             __syncthreads();
             add_rows(rows, min(kStartRows, win - r0));
         }
