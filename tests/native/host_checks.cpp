@@ -146,6 +146,19 @@ static void check_plans() {
     d.img = buf + 1;
     a = page_args(d, 14, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
     CHECK(a.row_aligned == 0 && a.lo == 7 && a.hi == 6, "unaligned args, even window");
+    // the aligned body keeps 32-bit per-thread offsets (8 rows plus a row's
+    // bytes): pitches of 2^28 or more take the general body
+    d.img = buf;
+    d.pitch_in = (int64_t)1 << 28;
+    d.pitch_out = 64;
+    a = page_args(d, 15, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
+    CHECK(a.row_aligned == 0, "input pitch 2^28: general body");
+    d.pitch_in = ((int64_t)1 << 28) - 16;
+    a = page_args(d, 15, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
+    CHECK(a.row_aligned == 1, "input pitch below 2^28: aligned body");
+    d.pitch_out = (int64_t)1 << 28;
+    a = page_args(d, 15, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
+    CHECK(a.row_aligned == 0, "output pitch 2^28: general body");
 }
 
 int main() {

@@ -116,3 +116,32 @@ def test_batch_of_crops_equals_single_calls(bz, use_graph):
         torch.cuda.synchronize()
         for (crop, out, *_), ref in zip(jobs, singles):
             assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("pitch_in,pitch_out", [((1 << 28) - 16, (1 << 28) - 8), (1 << 28, 4096), (4096, 1 << 28)])
+def test_pitches_near_the_aligned_body_limit(bz, oracle_mod, pitch_in, pitch_out):
+    """Rows 2^28 - 16 bytes apart still take the aligned body, whose staging
+    loads and output stores use 32-bit offsets from a step's first row (up to
+    7 pitches plus a row); a pitch of 2^28 on either side takes the general
+    body.  18 rows (two full 8-row blocks and a ragged one), against the
+    oracle, with the bytes between output rows untouched."""
+    from oracle.compare import compare_out
+    H, W = 18, 272
+    host = big_page(H, W, 1, seed=71)
+    print(f"pitch_in {pitch_in} pitch_out {pitch_out}", flush=True)
+    src = torch.zeros((H - 1) * pitch_in + W, dtype=torch.uint8, device="cuda")
+    img = torch.as_strided(src, (H, W), (pitch_in, 1))
+    img.copy_(torch.from_numpy(host).cuda())
+    dst = torch.zeros((H - 1) * pitch_out + W, dtype=torch.uint8, device="cuda")
+    out = torch.as_strided(dst, (H, W), (pitch_out, 1))
+    for rule, k, win in ((0, 0.5, 15), (1, -0.2, 31)):
+        dst.zero_()
+        bz.binarize(img, win, f32(k), 128.0, rule, out=out)
+        torch.cuda.synchronize()
+        ref = oracle_mod.binarize(host, win, f32(k), 128.0, rule)
+        rep = compare_out(out.cpu().numpy(), ref.out, ref.gray, ref.t)
+        assert rep["ok"], (pitch_in, pitch_out, rule, win, rep)
+        # nothing written between the output rows: the whole buffer sums to the rows' sum
+        assert int(dst.sum(dtype=torch.int64)) == int(out.sum(dtype=torch.int64))
+    del src, dst
+    torch.cuda.empty_cache()
