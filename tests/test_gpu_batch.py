@@ -138,6 +138,37 @@ def test_blocks_layout_pages_in_a_small_cap_batch(bz, oracle_mod, use_graph):
             assert compare_out(out, ref.out, ref.gray, ref.t)["ok"], (img.shape, win, rule)
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_every_occupancy_class_in_one_batch(bz, oracle_mod, use_graph):
+    """With the largest LDS cap, RGB pages at win 15, 61, 101 and 151-201 need
+    the LDS share of 4, 3, 2 and 1 workgroups per CU: one batch makes a
+    launch per class (plus the blocks launches of the wide gray pages and a
+    128-column ring page), one after another.  Every page equals its
+    single-page run, and the oracle where it finishes quickly."""
+    import pagegen
+    from oracle.compare import compare_out
+    rng = np.random.default_rng(77)
+    spec = [(3, 15, 0, None), (3, 61, 1, None), (3, 101, 0, None), (3, 151, 1, None), (3, 201, 0, None),
+            (1, 101, 0, None), (1, 151, 1, None), (3, 101, 1, (128, 64)), (1, 31, 0, None)]
+    jobs, dev = [], []
+    for i, (C, win, rule, tile) in enumerate(spec):
+        H, W = int(rng.integers(60, 420)), int(rng.integers(60, 600))
+        k = f32(float(rng.uniform(-0.3, 0.6)))
+        img = pagegen.page(H, W, max(1, pagegen.strokes_for(H, W)), seed=7700 + i, channels=C)
+        jobs.append((img, win, k, 128.0, rule))
+        t = torch.from_numpy(img).cuda()
+        dev.append((t, torch.full(img.shape[:2], 7, dtype=torch.uint8, device="cuda"), win, k, 128.0, rule, tile))
+    with bz.Batch(16, lds_cap=163776) as B:
+        B.run(dev, use_graph=use_graph)
+        torch.cuda.synchronize()
+    for (img, win, k, R, rule), d in zip(jobs, dev):
+        out = d[1].cpu().numpy()
+        assert np.array_equal(out, single(bz, img, win, k, R, rule)), (img.shape, win, rule)
+        if img.shape[0] * img.shape[1] * min(win, img.shape[0]) * min(win, img.shape[1]) < 3e8:
+            ref = oracle_mod.binarize(img, win, k, R, rule)
+            assert compare_out(out, ref.out, ref.gray, ref.t)["ok"], (img.shape, win, rule)
+
+
 def test_graph_recaptures_when_the_kernel_groups_change(bz):
     """Graph mode on one batch object: a batch with blocks pages, then one
     with ring pages only (fewer kernels in the graph), then the first again;
