@@ -155,7 +155,7 @@ def batch_jobs(name: str, dev):
 
 
 def run_batch_workload(name: str, reps: int, lds_cap: int = 0, tile_h: int = 0) -> dict:
-    """Per-image launches vs one persistent launch (direct and graph replay)
+    """Per-image launches vs the batched launch (direct and graph replay)
     on the same device-resident pages; outputs checked identical."""
     import torch
 

@@ -320,7 +320,7 @@ def _page_struct(job, i: int) -> _Page:
 
 
 def batch(jobs, stream: torch.cuda.Stream | None = None) -> None:
-    """Binarize many pages in one persistent launch through the one-call
+    """Binarize many pages in a few persistent launches through the one-call
     ``binarize_batch`` (library-managed batch objects).  ``jobs`` as for
     ``Batch.run``; the tensors must stay alive until the stream has
     finished the batch."""
@@ -338,7 +338,8 @@ def batch(jobs, stream: torch.cuda.Stream | None = None) -> None:
 
 
 class Batch:
-    """Many pages in one persistent launch (``binarize_batch_*`` in the C ABI).
+    """Many pages in a few persistent launches (``binarize_batch_*`` in the C ABI:
+    one per tile group and occupancy class, one after another).
 
     ``run(jobs)`` takes a list of ``(img, out, win, k, R, rule)`` or
     ``(img, out, win, k, R, rule, (tile_w, tile_h))`` tuples of CUDA tensors
