@@ -225,4 +225,60 @@ inline PageArgs page_args(const ImageDesc &d, int win, float k, float R, int rul
     return a;
 }
 
+// ------------------------------------------------------------ batch plans
+//
+// Pages run in launches keyed by kernel group and occupancy class, launched
+// one after another on the caller's stream.  Groups 0 and 1 hold the pages
+// in the ring layout with 256- and 128-column tiles, groups 2..5 the gray
+// pages in the blocks layout (those whose ring would exceed a quarter of
+// the CU's LDS), one group per tile variant: 2 + (tile_w == 256) * 2 + rule.
+// Tile variant of a ring page within its group, 0..3:
+// (channels == 3) * 2 + rule.  The class of a page is the highest number of
+// workgroups per CU (4, 3, 2, 1) whose share of the LDS holds its tile; a
+// launch reserves that share per workgroup, so pages of narrow windows run
+// at four workgroups per CU even when wider ones share the batch.
+constexpr int kGroups = 6;
+constexpr int kClasses = 4;
+constexpr int kLaunches = kGroups * kClasses;  // launch key: group * kClasses + class
+inline int kind_of(int channels, int rule) { return (channels == 3) * 2 + rule; }
+inline bool blk_group(int g) { return g >= 2; }
+inline int group_of(int tile_w, int rule, bool blocks) {
+    return blocks ? 2 + (tile_w == 256) * 2 + rule : (tile_w == 256 ? 0 : 1);
+}
+
+// LDS the batch kernels declare statically (the item slot), rounded up.
+constexpr int kStaticLds = 64;
+// Dynamic LDS of a workgroup of class c (kClasses - c workgroups per CU),
+// a multiple of 16 bytes.
+inline int class_lds(int c) { return (kMaxLds / (kClasses - c) - kStaticLds) & ~15; }
+// Class of a tile that needs `lds` bytes (-1: more than one CU holds).
+inline int class_of(int lds) {
+    for (int c = 0; c < kClasses; ++c)
+        if (lds <= class_lds(c)) return c;
+    return -1;
+}
+
+// Tile, layout and LDS need of one page within the batch's LDS cap: the
+// caller's width if it fits, else 256 columns when the window allows, else
+// 128; tile_h 128 unless given.  Gray pages whose ring would exceed a
+// quarter of the CU's LDS take the blocks layout (as in the single-page
+// kernel, which also weighs the page's tile count: in a batch the pages share
+// the GPU, so occupancy always counts), every other page the ring.
+inline int page_tile(const bz_page &p, int lds_cap, int *tw, int *th, bool *blk, int *lds) {
+    auto fits = [&](int w) {
+        return tile_fits(w, p.win, p.channels) && tile_lds_bytes(w, p.win, p.channels) <= lds_cap;
+    };
+    int w = p.tile_w, h = p.tile_h;
+    if (w == 0) w = fits(256) ? 256 : 128;
+    if (h == 0) h = 128;
+    if (w != 128 && w != 256) return BZ_ERR_TILE;
+    if (h < kRowsPerStep || h > 4096 || h % kRowsPerStep) return BZ_ERR_TILE;
+    if (!fits(w)) return BZ_ERR_TILE;
+    *tw = w;
+    *th = h;
+    *blk = gray_blocks(w, p.win, p.channels);
+    *lds = tile_lds_bytes(w, p.win, p.channels);
+    return BZ_OK;
+}
+
 }  // namespace bz

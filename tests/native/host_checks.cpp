@@ -161,8 +161,57 @@ static void check_plans() {
     CHECK(a.row_aligned == 0, "output pitch 2^28: general body");
 }
 
+// Batch plans: occupancy classes, tile width, layout and launch group of a
+// page, and the refusals.
+static void check_batch_plans() {
+    CHECK(class_lds(0) == 40896 && class_lds(1) == 54544 && class_lds(2) == 81856 && class_lds(3) == 163776,
+          "class shares %d %d %d %d", class_lds(0), class_lds(1), class_lds(2), class_lds(3));
+    for (int c = 0; c < kClasses; ++c)
+        CHECK((kClasses - c) * (class_lds(c) + kStaticLds) <= kMaxLds && class_lds(c) % 16 == 0, "class %d fits", c);
+    CHECK(class_of(40896) == 0 && class_of(40897) == 1 && class_of(54544) == 1 && class_of(54545) == 2 &&
+              class_of(81856) == 2 && class_of(81857) == 3 && class_of(163776) == 3 && class_of(163777) == -1,
+          "class boundaries");
+    CHECK(group_of(256, 0, false) == 0 && group_of(128, 1, false) == 1 && group_of(128, 0, true) == 2 &&
+              group_of(128, 1, true) == 3 && group_of(256, 0, true) == 4 && group_of(256, 1, true) == 5,
+          "groups");
+    CHECK(blk_group(2) && blk_group(5) && !blk_group(0) && !blk_group(1), "blocks groups");
+    auto plan = [](int C, int win, int cap, int tw_req, int th_req, int *tw, int *th, bool *blk, int *lds) {
+        bz_page p{};
+        p.H = 100;
+        p.W_img = 100;
+        p.channels = C;
+        p.win = win;
+        p.tile_w = tw_req;
+        p.tile_h = th_req;
+        return page_tile(p, cap, tw, th, blk, lds);
+    };
+    int tw = 0, th = 0, lds = 0;
+    bool blk = false;
+    const int cap = class_lds(2);  // the default
+    CHECK(plan(1, 15, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 256 && th == 128 && !blk && lds == 32752 &&
+              class_of(lds) == 0,
+          "gray 15: ring, 4 per CU");
+    CHECK(plan(1, 61, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 256 && blk && class_of(lds) == 0,
+          "gray 61: blocks, 4 per CU (%d)", lds);
+    CHECK(plan(1, 255, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 128 && blk && class_of(lds) == 0,
+          "gray 255: 128-column blocks (%d)", lds);
+    CHECK(plan(3, 61, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 256 && !blk && class_of(lds) == 1,
+          "rgb 61: ring, 3 per CU (%d)", lds);
+    CHECK(plan(3, 151, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 128 && !blk && class_of(lds) == 2,
+          "rgb 151 at the default cap: 128 columns, 2 per CU (%d)", lds);
+    CHECK(plan(3, 201, class_lds(3), 0, 0, &tw, &th, &blk, &lds) == BZ_OK && tw == 256 && class_of(lds) == 3,
+          "rgb 201 at the largest cap: 256 columns, 1 per CU (%d)", lds);
+    CHECK(plan(3, 255, cap, 0, 0, &tw, &th, &blk, &lds) == BZ_ERR_TILE, "rgb 255 needs more than the cap");
+    CHECK(plan(1, 31, cap, 128, 64, &tw, &th, &blk, &lds) == BZ_OK && tw == 128 && th == 64 && !blk,
+          "caller's tile");
+    CHECK(plan(1, 31, cap, 64, 0, &tw, &th, &blk, &lds) == BZ_ERR_TILE, "tile width 64 refused");
+    CHECK(plan(1, 31, cap, 0, 12, &tw, &th, &blk, &lds) == BZ_ERR_TILE, "tile height 12 refused");
+    CHECK(plan(1, 31, class_lds(0), 0, 0, &tw, &th, &blk, &lds) == BZ_OK && lds <= class_lds(0), "small cap");
+}
+
 int main() {
     check_regions();
+    check_batch_plans();
     check_parameter_range();
     check_decision();
     check_images();
