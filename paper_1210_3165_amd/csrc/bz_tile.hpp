@@ -118,6 +118,25 @@ __device__ __forceinline__ glb_u8 *uniform_global(uint8_t *p) {
     return (glb_u8 *)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Unaligned views (alignment 1) for the wide accesses of the interior tiles
+// of pages whose rows are not 16-byte aligned: gfx950 loads and stores them
+// whole (global memory runs in unaligned access mode under ROCm).
+typedef unsigned int u32x4_a1 __attribute__((ext_vector_type(4), aligned(1)));
+typedef unsigned int u32x2_a1 __attribute__((ext_vector_type(2), aligned(1)));
+typedef __attribute__((address_space(1))) u32x2_a1 glb_u32x2_a1;
+
+// How a tile stages its input rows and stores its outputs:
+//   kAligned  rows 16-byte aligned, a multiple of 16 pixels wide, pitches
+//             below 2^28 (every tile of such a page): 16-byte loads and
+//             8-byte stores from a uniform row address plus 32-bit offsets;
+//   kWide     other pages, tiles whose staged columns (and the word past
+//             them) lie inside the row: unaligned 16-byte loads and 8-byte
+//             stores from a uniform row address plus 64-bit offsets;
+//   kEdge     other pages, tiles reaching past the row's ends: word loads
+//             clamped into the row, byte masks, byte stores at ragged ends.
+// All three give identical bytes.
+enum { kEdge = 0, kWide = 1, kAligned = 2 };
+
 // ---------------------------------------------------------------- staging
 //
 // A staging job is 16 consecutive pixels of one image row.  Its raw bytes are
@@ -208,16 +227,20 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
 // 16-byte aligned and a multiple of 16 pixels wide, so every chunk lies wholly
 // inside or wholly outside the image: chunks are loaded whole with one 16-byte
 // load, and chunks outside load a clamped chunk and store zeros.
-template <int C, bool INT>
+template <int C, int BODY>
 struct Stager {
+    static constexpr bool INT = BODY == kAligned;
+    static constexpr bool WIDE = BODY == kWide;
     RawChunk<C> k;
     int job_row, job_q;  // job_row >= kRowsPerStep: this thread has no job
     bool in_image;
     // INT bodies: the job's byte offsets from the first row of its block
     // and from its row (32-bit offsets: pitches are below 2^28 there), and
     // whether its chunk lies inside the image's columns; cols_in: every
-    // chunk of the tile does.
+    // chunk of the tile does.  WIDE bodies: the same offsets in 64 bits
+    // (any pitch; every chunk of the tile lies inside its row).
     uint32_t voff, xoff;
+    uint64_t voff64, xoff64;
     bool col_in, cols_in;
     bool zero_free;  // the last fetch staged rows and chunks all inside the image
 
@@ -234,9 +257,42 @@ struct Stager {
             xoff = (uint32_t)(C * min(max(xs, 0), a.W - 16));
             voff = (uint32_t)job_row * (uint32_t)a.pitch_in + xoff;
         }
+        if (WIDE) {
+            xoff64 = (uint64_t)(C * (xr0 + 16 * job_q));
+            voff64 = (uint64_t)job_row * (uint64_t)a.pitch_in + xoff64;
+        }
     }
 
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
+        if (WIDE) {
+            // as in the aligned body below, with 64-bit offsets and
+            // unaligned 16-byte loads; every chunk lies inside its row
+            const bool inside = row0 >= 0 && row0 + nrows <= a.H;  // uniform
+            const int rb = min(max(row0, 0), a.H - 1);
+            uint64_t off = voff64;
+            in_image = true;
+            if (!inside) {
+                const int row = row0 + job_row;
+                const int rc = min(max(row, 0), a.H - 1);
+                off = (uint64_t)(rc - rb) * (uint64_t)a.pitch_in + xoff64;
+                in_image = row >= 0 && row < a.H;
+            }
+            zero_free = inside;
+            if (job_row < nrows) {
+                const uint8_t *blk = a.img + (size_t)rb * (size_t)a.pitch_in;  // uniform
+                const u32x4_a1 *q = reinterpret_cast<const u32x4_a1 *>(blk + off);
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const u32x4_a1 v = q[i];
+                    k.w[4 * i] = v.x;
+                    k.w[4 * i + 1] = v.y;
+                    k.w[4 * i + 2] = v.z;
+                    k.w[4 * i + 3] = v.w;
+                }
+                k.sh = 0;
+            }
+            return;
+        }
         if (INT) {
             // Every job loads from one uniform row address, that of the
             // block's first row clamped into the image, plus a 32-bit offset:
@@ -290,7 +346,7 @@ struct Stager {
     // run on every step).
     template <class P>
     __device__ __forceinline__ void put(const PageArgs &a, P *p, int xr0, bool clamp) const {
-        const uint4 v = chunk_gray<C, INT>(k, xr0 + 16 * job_q, a.W, clamp);
+        const uint4 v = chunk_gray<C, BODY != kEdge>(k, xr0 + 16 * job_q, a.W, clamp);
         *p = u32x4{v.x, v.y, v.z, v.w};
         if (!zero_free) {
             asm volatile("");
@@ -475,6 +531,17 @@ __device__ __forceinline__ void store_nt4(glb_u8 *p, uint32_t w) {
     __builtin_nontemporal_store(w, (__attribute__((address_space(1))) uint32_t *)p);
 }
 
+// The same at any byte address (interior tiles of unaligned pages).
+typedef uint32_t u32_a1 __attribute__((aligned(1)));
+__device__ __forceinline__ void store_nt8_a1(glb_u8 *p, uint32_t lo, uint32_t hi) {
+    const u32x2_a1 v = {lo, hi};
+    __builtin_nontemporal_store(v, (glb_u32x2_a1 *)p);
+}
+
+__device__ __forceinline__ void store_nt4_a1(glb_u8 *p, uint32_t w) {
+    __builtin_nontemporal_store(w, (__attribute__((address_space(1))) u32_a1 *)p);
+}
+
 // Store OPT output bytes (packed little-endian in w) at columns [xs, xs+OPT)
 // of an output row, skipping columns >= W.
 template <int OPT>
@@ -556,7 +623,7 @@ __device__ __forceinline__ void load_v2(const uint32_t *row, int width, int h, u
     }
 }
 
-template <int TW, int C, int RULE, bool STATS, bool INT, bool BLK>
+template <int TW, int C, int RULE, bool STATS, int BODY, bool BLK>
 __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_t *smem) {
     constexpr int RB = kRowsPerStep;
     constexpr int TPR = kThreadsPerRow;
@@ -585,9 +652,12 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     uint32_t *Vb2 = Va2 + RB * VAP;
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
-    // Clamp loads and mask bytes unless columns [xr0, xr0 + rp) and the one
-    // extra word a chunk may read past its last byte all lie inside the row.
-    const bool clamp = !INT && (xr0 < 0 || xr0 + rp + 4 > a.W);
+    // Clamp loads and mask bytes in edge tiles: some of columns [xr0, xr0 +
+    // rp), or the one extra word a chunk may read past its last byte, lie
+    // outside the row (run_tile sends such tiles of unaligned pages to the
+    // kEdge body).
+    constexpr bool INT = BODY == kAligned;
+    constexpr bool clamp = BODY == kEdge;
 
     // Wave priorities.  The waves of a CU come from several workgroups, each
     // of which alternates a short phase that every other wave of it waits
@@ -640,7 +710,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     // Rows of the next step, in flight while this one computes: the
     // entering rows (and in the blocks layout the leaving and centre rows
     // too).
-    Stager<C, INT> pre, pre_l, pre_c;
+    Stager<C, BODY> pre, pre_l, pre_c;
     pre.init(a, xr0);
     if (blocks) {
         pre_l.init(a, xr0);
@@ -653,7 +723,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // round's loads are issued as soon as this round's rows are stored,
         // so they are in flight across the barrier and the summing.
         constexpr int NS = kStartRows / RB;
-        Stager<C, INT> st[NS];
+        Stager<C, BODY> st[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
         // loads of the rounds starting at r (with the first step's blocks
@@ -698,7 +768,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
         // blocks, and go in behind the start-up rows (slots the start-up
         // reads do not touch).
         constexpr int NS = C == 1 ? 4 : 2;  // blocks in flight (registers per block: 5 or 13 words)
-        Stager<C, INT> st[NS];
+        Stager<C, BODY> st[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) st[u].init(a, xr0);
         for (int r0 = 0; r0 < win; r0 += NS * RB) {
@@ -740,8 +810,10 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 
     const int hr = tid / TPR, hs = tid % TPR;
     // INT bodies: this thread's output bytes relative to the step's first
-    // output row (pitches are below 2^28 there)
+    // output row (pitches are below 2^28 there); WIDE bodies: the same in
+    // 64 bits
     const uint32_t out_off = (uint32_t)hr * (uint32_t)a.pitch_out + (uint32_t)(X0 + hs * OPT);
+    const uint64_t out_off64 = (uint64_t)hr * (uint64_t)a.pitch_out + (uint64_t)(X0 + hs * OPT);
     // Steps whose windows all span win rows, in a 256-column block of the
     // page (counted from column 0) whose windows all span win columns, are
     // decided with the per-tile Sauvola constants; every other pixel takes
@@ -957,6 +1029,12 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                     else
                         store_nt4(p, ow[0]);
                 }
+            } else if (BODY == kWide) {  // every output of an interior tile lies inside the row
+                glb_u8 *p = uniform_global(a.out + (size_t)y0 * (size_t)a.pitch_out) + out_off64;
+                if (OPT == 8)
+                    store_nt8_a1(p, ow[0], ow[OPT / 4 - 1]);
+                else
+                    store_nt4_a1(p, ow[0]);
             } else {
                 store_row<OPT>(a.out + (size_t)y * (size_t)a.pitch_out, xs, a.W, ow);
             }
@@ -983,18 +1061,26 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 // launch): input rows 16-byte aligned and a multiple of 16 pixels wide, so
 // every 16-pixel chunk lies wholly inside or outside the image and staging
 // loads whole chunks with no per-byte masking; output rows 8-byte aligned, so
-// every thread stores its outputs with one store.  Both bodies produce
-// identical bytes.  In either, tiles whose windows all span win columns decide
-// steps whose windows also span win rows with the per-tile constants, and
-// every other step with per-pixel n.  BLK selects the blocks layout of the
-// input rows (gray pages; see gray_blocks), a separate kernel so that each
-// layout gets its own register allocation.
+// every thread stores its outputs with one store.  Other pages take, per tile
+// (a uniform choice), the wide body when every staged column lies inside the
+// row (unaligned 16-byte loads and 8-byte stores), else the edge body.  All
+// bodies produce identical bytes.  In each, tiles whose windows all span win
+// columns decide steps whose windows also span win rows with the per-tile
+// constants, and every other step with per-pixel n.  BLK selects the blocks
+// layout of the input rows (gray pages; see gray_blocks), a separate kernel
+// so that each layout gets its own register allocation.
 template <int TW, int C, int RULE, bool STATS, bool BLK = false>
 __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *smem) {
-    if (a.row_aligned)
-        process_tile<TW, C, RULE, STATS, true, BLK>(a, tile, smem);
+    if (a.row_aligned) {
+        process_tile<TW, C, RULE, STATS, kAligned, BLK>(a, tile, smem);
+        return;
+    }
+    const int X0 = (tile % a.tiles_x) * TW;
+    const int xr0 = floor16(X0 - a.lo - 1);  // as in process_tile
+    if (xr0 < 0 || xr0 + a.rp + 4 > a.W)
+        process_tile<TW, C, RULE, STATS, kEdge, BLK>(a, tile, smem);
     else
-        process_tile<TW, C, RULE, STATS, false, BLK>(a, tile, smem);
+        process_tile<TW, C, RULE, STATS, kWide, BLK>(a, tile, smem);
 }
 
 template <int TW, int C, int RULE, bool STATS, bool BLK>
