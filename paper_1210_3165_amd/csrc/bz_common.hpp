@@ -53,6 +53,7 @@ struct PageArgs {
     int row_aligned;  // input rows 16-byte aligned and a multiple of 16 pixels, output rows 8-byte
                       // aligned, both pitches below 2^28
     int blocks;       // gray page in the blocks layout (see gray_blocks)
+    int small_pitch;  // both pitches below 2^28 (per-thread offsets of 8 rows fit 32 bits)
 };
 
 BZ_HD inline int round_up(int x, int m) { return (x + m - 1) / m * m; }

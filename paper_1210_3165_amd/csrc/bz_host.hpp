@@ -215,11 +215,12 @@ inline PageArgs page_args(const ImageDesc &d, int win, float k, float R, int rul
     a.rp = ring_pitch(tile_w, win);
     a.depth = ring_rows(tile_w, win, d.C, allow_blocks);
     a.blocks = gray_blocks(tile_w, win, d.C, allow_blocks) ? 1 : 0;
-    // (pitches below 2^28 also keep the aligned body's per-thread offsets
-    // from a step's first row, at most 8 rows plus a row's bytes, in 32 bits)
-    a.row_aligned = (((uintptr_t)d.img & 15) == 0 && d.pitch_in % 16 == 0 && ((int64_t)d.W * d.C) % 16 == 0 &&
-                     ((uintptr_t)d.out & 7) == 0 && d.pitch_out % 8 == 0 && d.pitch_in < ((int64_t)1 << 28) &&
-                     d.pitch_out < ((int64_t)1 << 28))
+    // (pitches below 2^28 keep the per-thread offsets of the aligned and
+    // wide bodies from a step's first row, at most 8 rows plus a row's bytes,
+    // in 32 bits)
+    a.small_pitch = (d.pitch_in < ((int64_t)1 << 28) && d.pitch_out < ((int64_t)1 << 28)) ? 1 : 0;
+    a.row_aligned = (a.small_pitch && ((uintptr_t)d.img & 15) == 0 && d.pitch_in % 16 == 0 &&
+                     ((int64_t)d.W * d.C) % 16 == 0 && ((uintptr_t)d.out & 7) == 0 && d.pitch_out % 8 == 0)
                         ? 1
                         : 0;
     return a;

@@ -129,11 +129,12 @@ typedef __attribute__((address_space(1))) u32x2_a1 glb_u32x2_a1;
 //   kAligned  rows 16-byte aligned, a multiple of 16 pixels wide, pitches
 //             below 2^28 (every tile of such a page): 16-byte loads and
 //             8-byte stores from a uniform row address plus 32-bit offsets;
-//   kWide     other pages, tiles whose staged columns (and the word past
-//             them) lie inside the row: unaligned 16-byte loads and 8-byte
-//             stores from a uniform row address plus 64-bit offsets;
-//   kEdge     other pages, tiles reaching past the row's ends: word loads
-//             clamped into the row, byte masks, byte stores at ragged ends.
+//   kWide     other pages with pitches below 2^28, tiles whose staged
+//             columns (and the word past them) lie inside the row: unaligned
+//             16-byte loads and 8-byte stores from a uniform row address plus
+//             32-bit offsets;
+//   kEdge     every other tile: word loads clamped into the row, byte masks,
+//             byte stores at the ragged end of a row.
 // All three give identical bytes.
 enum { kEdge = 0, kWide = 1, kAligned = 2 };
 
@@ -173,21 +174,24 @@ __device__ __forceinline__ void fetch_chunk(RawChunk<C> &k, const uint8_t *__res
         k.sh = 0;
         return;
     }
-    const uintptr_t ad = (uintptr_t)rowp + (uintptr_t)(intptr_t)(C * xs);
-    k.sh = (uint32_t)(ad & 3);
-    uintptr_t q = ad - k.sh;
+    // word offsets relative to the row pointer (the row's bytes are
+    // [0, C W)), so every address derives from the image pointer and the
+    // loads stay global
+    const int r = (int)((uintptr_t)rowp & 3);  // the row's first byte within its word
+    const int o = C * xs;                      // the chunk's first byte
+    k.sh = (uint32_t)((r + o) & 3);
+    const int q = o - (int)k.sh;               // word-aligned (relative to the row's words)
     if (clamp) {
-        const uintptr_t first = (uintptr_t)rowp & ~(uintptr_t)3;
-        const uintptr_t last = ((uintptr_t)rowp + (uintptr_t)(C * W) - 1) & ~(uintptr_t)3;
+        const int first = -r;                            // word holding byte 0
+        const int last = ((r + C * W - 1) & ~3) - r;     // word holding byte C W - 1
 #pragma unroll
         for (int i = 0; i < RawChunk<C>::NW; ++i) {
-            uintptr_t qi = q + 4 * i;
-            qi = qi < first ? first : (qi > last ? last : qi);
-            k.w[i] = *(const uint32_t *)qi;
+            const int qi = min(max(q + 4 * i, first), last);
+            k.w[i] = *(const uint32_t *)(rowp + qi);
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < RawChunk<C>::NW; ++i) k.w[i] = ((const uint32_t *)q)[i];
+        for (int i = 0; i < RawChunk<C>::NW; ++i) k.w[i] = *(const uint32_t *)(rowp + q + 4 * i);
     }
 }
 
@@ -234,13 +238,11 @@ struct Stager {
     RawChunk<C> k;
     int job_row, job_q;  // job_row >= kRowsPerStep: this thread has no job
     bool in_image;
-    // INT bodies: the job's byte offsets from the first row of its block
-    // and from its row (32-bit offsets: pitches are below 2^28 there), and
-    // whether its chunk lies inside the image's columns; cols_in: every
-    // chunk of the tile does.  WIDE bodies: the same offsets in 64 bits
-    // (any pitch; every chunk of the tile lies inside its row).
+    // INT and WIDE bodies: the job's byte offsets from the first row of its
+    // block and from its row (32-bit offsets: pitches are below 2^28 there),
+    // and whether its chunk lies inside the image's columns; cols_in: every
+    // chunk of the tile does (always in WIDE bodies).
     uint32_t voff, xoff;
-    uint64_t voff64, xoff64;
     bool col_in, cols_in;
     bool zero_free;  // the last fetch staged rows and chunks all inside the image
 
@@ -250,54 +252,22 @@ struct Stager {
         job_q = (int)threadIdx.x - job_row * nq;
         in_image = true;
         zero_free = false;
-        if (INT) {
+        if (INT || WIDE) {
             const int xs = xr0 + 16 * job_q;
-            col_in = xs >= 0 && xs < a.W;
-            cols_in = xr0 >= 0 && xr0 + a.rp <= a.W;
-            xoff = (uint32_t)(C * min(max(xs, 0), a.W - 16));
+            col_in = WIDE || (xs >= 0 && xs < a.W);
+            cols_in = WIDE || (xr0 >= 0 && xr0 + a.rp <= a.W);
+            xoff = (uint32_t)(C * (WIDE ? xs : min(max(xs, 0), a.W - 16)));
             voff = (uint32_t)job_row * (uint32_t)a.pitch_in + xoff;
-        }
-        if (WIDE) {
-            xoff64 = (uint64_t)(C * (xr0 + 16 * job_q));
-            voff64 = (uint64_t)job_row * (uint64_t)a.pitch_in + xoff64;
         }
     }
 
     __device__ __forceinline__ void fetch(const PageArgs &a, int row0, int nrows, int xr0, bool clamp) {
-        if (WIDE) {
-            // as in the aligned body below, with 64-bit offsets and
-            // unaligned 16-byte loads; every chunk lies inside its row
-            const bool inside = row0 >= 0 && row0 + nrows <= a.H;  // uniform
-            const int rb = min(max(row0, 0), a.H - 1);
-            uint64_t off = voff64;
-            in_image = true;
-            if (!inside) {
-                const int row = row0 + job_row;
-                const int rc = min(max(row, 0), a.H - 1);
-                off = (uint64_t)(rc - rb) * (uint64_t)a.pitch_in + xoff64;
-                in_image = row >= 0 && row < a.H;
-            }
-            zero_free = inside;
-            if (job_row < nrows) {
-                const uint8_t *blk = a.img + (size_t)rb * (size_t)a.pitch_in;  // uniform
-                const u32x4_a1 *q = reinterpret_cast<const u32x4_a1 *>(blk + off);
-#pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const u32x4_a1 v = q[i];
-                    k.w[4 * i] = v.x;
-                    k.w[4 * i + 1] = v.y;
-                    k.w[4 * i + 2] = v.z;
-                    k.w[4 * i + 3] = v.w;
-                }
-                k.sh = 0;
-            }
-            return;
-        }
-        if (INT) {
+        if (INT || WIDE) {
             // Every job loads from one uniform row address, that of the
             // block's first row clamped into the image, plus a 32-bit offset:
             // fixed when every row of the block lies inside the image (the
-            // usual case), else from the job's own clamped row.
+            // usual case), else from the job's own clamped row.  (WIDE:
+            // unaligned loads; every chunk lies inside its row.)
             const bool inside = row0 >= 0 && row0 + nrows <= a.H;  // uniform
             const int rb = min(max(row0, 0), a.H - 1);
             uint32_t off = voff;
@@ -311,10 +281,10 @@ struct Stager {
             zero_free = inside && cols_in;
             if (job_row < nrows) {
                 const uint8_t *blk = a.img + (size_t)rb * (size_t)a.pitch_in;  // uniform
-                const uint4 *q = reinterpret_cast<const uint4 *>(blk + off);
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
-                    const uint4 v = q[i];
+                    const u32x4 v = WIDE ? (u32x4)reinterpret_cast<const u32x4_a1 *>(blk + off)[i]
+                                         : reinterpret_cast<const u32x4 *>(blk + off)[i];
                     k.w[4 * i] = v.x;
                     k.w[4 * i + 1] = v.y;
                     k.w[4 * i + 2] = v.z;
@@ -546,24 +516,16 @@ __device__ __forceinline__ void store_nt4_a1(glb_u8 *p, uint32_t w) {
 // of an output row, skipping columns >= W.
 template <int OPT>
 __device__ __forceinline__ void store_row(uint8_t *rowp, int xs, int W, const uint32_t (&w)[OPT / 4]) {
-    if (xs + OPT <= W) {
-        uint8_t *p = rowp + xs;
-        const uintptr_t ad = (uintptr_t)p;
-        if ((ad & (OPT - 1)) == 0) {
-            if (OPT == 8)
-                store_nt8(p, w[0], w[OPT / 4 - 1]);
-            else
-                store_nt4(p, w[0]);
-            return;
-        }
-        if ((ad & 3) == 0) {
-#pragma unroll
-            for (int i = 0; i < OPT / 4; ++i) store_nt4(p + 4 * i, w[i]);
-            return;
-        }
+    if (xs + OPT <= W) {  // one store at any byte address
+        glb_u8 *p = (glb_u8 *)(rowp + xs);
+        if (OPT == 8)
+            store_nt8_a1(p, w[0], w[OPT / 4 - 1]);
+        else
+            store_nt4_a1(p, w[0]);
+        return;
     }
 #pragma unroll
-    for (int j = 0; j < OPT; ++j)
+    for (int j = 0; j < OPT; ++j)  // the ragged end of the row
         if (xs + j < W) rowp[xs + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
 }
 
@@ -809,11 +771,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     }
 
     const int hr = tid / TPR, hs = tid % TPR;
-    // INT bodies: this thread's output bytes relative to the step's first
-    // output row (pitches are below 2^28 there); WIDE bodies: the same in
-    // 64 bits
+    // INT and WIDE bodies: this thread's output bytes relative to the step's
+    // first output row (pitches are below 2^28 there)
     const uint32_t out_off = (uint32_t)hr * (uint32_t)a.pitch_out + (uint32_t)(X0 + hs * OPT);
-    const uint64_t out_off64 = (uint64_t)hr * (uint64_t)a.pitch_out + (uint64_t)(X0 + hs * OPT);
     // Steps whose windows all span win rows, in a 256-column block of the
     // page (counted from column 0) whose windows all span win columns, are
     // decided with the per-tile Sauvola constants; every other pixel takes
@@ -1030,7 +990,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                         store_nt4(p, ow[0]);
                 }
             } else if (BODY == kWide) {  // every output of an interior tile lies inside the row
-                glb_u8 *p = uniform_global(a.out + (size_t)y0 * (size_t)a.pitch_out) + out_off64;
+                glb_u8 *p = uniform_global(a.out + (size_t)y0 * (size_t)a.pitch_out) + out_off;
                 if (OPT == 8)
                     store_nt8_a1(p, ow[0], ow[OPT / 4 - 1]);
                 else
@@ -1063,7 +1023,8 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 // loads whole chunks with no per-byte masking; output rows 8-byte aligned, so
 // every thread stores its outputs with one store.  Other pages take, per tile
 // (a uniform choice), the wide body when every staged column lies inside the
-// row (unaligned 16-byte loads and 8-byte stores), else the edge body.  All
+// row and both pitches are below 2^28 (unaligned 16-byte loads and 8-byte
+// stores), else the edge body.  All
 // bodies produce identical bytes.  In each, tiles whose windows all span win
 // columns decide steps whose windows also span win rows with the per-tile
 // constants, and every other step with per-pixel n.  BLK selects the blocks
@@ -1077,7 +1038,7 @@ __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *s
     }
     const int X0 = (tile % a.tiles_x) * TW;
     const int xr0 = floor16(X0 - a.lo - 1);  // as in process_tile
-    if (xr0 < 0 || xr0 + a.rp + 4 > a.W)
+    if (!a.small_pitch || xr0 < 0 || xr0 + a.rp + 4 > a.W)
         process_tile<TW, C, RULE, STATS, kEdge, BLK>(a, tile, smem);
     else
         process_tile<TW, C, RULE, STATS, kWide, BLK>(a, tile, smem);

@@ -158,7 +158,11 @@ static void check_plans() {
     CHECK(a.row_aligned == 1, "input pitch below 2^28: aligned body");
     d.pitch_out = (int64_t)1 << 28;
     a = page_args(d, 15, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
-    CHECK(a.row_aligned == 0, "output pitch 2^28: general body");
+    CHECK(a.row_aligned == 0 && a.small_pitch == 0, "output pitch 2^28: edge body only");
+    d.pitch_out = 4099;
+    d.img = buf + 3;
+    a = page_args(d, 15, 0.5f, 128.0f, BZ_SAUVOLA, 256, 64);
+    CHECK(a.row_aligned == 0 && a.small_pitch == 1, "unaligned rows, small pitches: wide interior tiles");
 }
 
 // Batch plans: occupancy classes, tile width, layout and launch group of a
