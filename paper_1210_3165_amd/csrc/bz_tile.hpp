@@ -129,12 +129,16 @@ typedef __attribute__((address_space(1))) u32x2_a1 glb_u32x2_a1;
 //   kAligned  rows 16-byte aligned, a multiple of 16 pixels wide, pitches
 //             below 2^28 (every tile of such a page): 16-byte loads and
 //             8-byte stores from a uniform row address plus 32-bit offsets;
-//   kWide     other pages with pitches below 2^28, tiles whose staged
-//             columns (and the word past them) lie inside the row: unaligned
-//             16-byte loads and 8-byte stores from a uniform row address plus
-//             32-bit offsets;
-//   kEdge     every other tile: word loads clamped into the row, byte masks,
-//             byte stores at the ragged end of a row.
+//   kWide     other pages at least 16 pixels wide with pitches below 2^28
+//             (every tile): unaligned 16-byte loads and 8-byte stores from a
+//             uniform row address plus 32-bit offsets.  Chunks start on
+//             multiples of 16 columns, so only the chunk that holds a row's
+//             last column can reach past it: that chunk loads the row's last
+//             16 pixels and moves them down in registers (shift_out), and
+//             outputs past the row end take byte stores;
+//   kEdge     pages narrower than 16 pixels or with larger pitches: word
+//             loads clamped into the row, byte masks, byte stores at the
+//             ragged end of a row.
 // All three give identical bytes.
 enum { kEdge = 0, kWide = 1, kAligned = 2 };
 
@@ -224,6 +228,17 @@ __device__ __forceinline__ uint4 chunk_gray(const RawChunk<C> &k, int xs, int W,
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+// Gray levels g of columns [W - 16, W) moved down so that byte j holds column
+// xs + j, for the chunk [xs, xs + 16) that holds column W - 1 (cut = xs + 16 - W
+// in 1..15): byte j takes byte j + cut, and the bytes past the row become 0.
+__device__ __forceinline__ u32x4 shift_out(u32x4 g, int cut) {
+    const uint64_t lo = (uint64_t)g.x | ((uint64_t)g.y << 32), hi = (uint64_t)g.z | ((uint64_t)g.w << 32);
+    const uint32_t sb = 8u * (uint32_t)cut;  // 8..120 bits
+    const uint64_t nlo = sb < 64 ? (lo >> sb) | (hi << (64 - sb)) : hi >> (sb - 64);
+    const uint64_t nhi = sb < 64 ? hi >> sb : 0;
+    return u32x4{(uint32_t)nlo, (uint32_t)(nlo >> 32), (uint32_t)nhi, (uint32_t)(nhi >> 32)};
+}
+
 // The job of this thread for a block of up to RB rows: row i = job / nq of
 // the block, chunk q = job % nq (nq = rp / 16 chunks per row).  RB * rp / 16
 // <= 256 gives at most one job per thread.  Rows outside the image load a clamped
@@ -240,10 +255,13 @@ struct Stager {
     bool in_image;
     // INT and WIDE bodies: the job's byte offsets from the first row of its
     // block and from its row (32-bit offsets: pitches are below 2^28 there),
-    // and whether its chunk lies inside the image's columns; cols_in: every
-    // chunk of the tile does (always in WIDE bodies).
+    // and whether its chunk starts inside the image's columns; cols_in: every
+    // chunk of the tile lies wholly inside; cut (WIDE): columns of the chunk
+    // past the row's end when it holds the row's last column, else 0 (the
+    // chunk then loads the row's last 16 pixels instead).
     uint32_t voff, xoff;
     bool col_in, cols_in;
+    int cut;
     bool zero_free;  // the last fetch staged rows and chunks all inside the image
 
     __device__ __forceinline__ void init(const PageArgs &a, int xr0) {
@@ -254,9 +272,10 @@ struct Stager {
         zero_free = false;
         if (INT || WIDE) {
             const int xs = xr0 + 16 * job_q;
-            col_in = WIDE || (xs >= 0 && xs < a.W);
-            cols_in = WIDE || (xr0 >= 0 && xr0 + a.rp <= a.W);
-            xoff = (uint32_t)(C * (WIDE ? xs : min(max(xs, 0), a.W - 16)));
+            col_in = xs >= 0 && xs < a.W;
+            cols_in = xr0 >= 0 && xr0 + a.rp <= a.W;
+            cut = WIDE && col_in && xs + 16 > a.W ? xs + 16 - a.W : 0;
+            xoff = (uint32_t)(C * min(max(xs, 0), a.W - 16));
             voff = (uint32_t)job_row * (uint32_t)a.pitch_in + xoff;
         }
     }
@@ -266,8 +285,8 @@ struct Stager {
             // Every job loads from one uniform row address, that of the
             // block's first row clamped into the image, plus a 32-bit offset:
             // fixed when every row of the block lies inside the image (the
-            // usual case), else from the job's own clamped row.  (WIDE:
-            // unaligned loads; every chunk lies inside its row.)
+            // usual case), else from the job's own clamped row.  Chunks
+            // outside the columns load a clamped chunk (stored as zeros).
             const bool inside = row0 >= 0 && row0 + nrows <= a.H;  // uniform
             const int rb = min(max(row0, 0), a.H - 1);
             uint32_t off = voff;
@@ -311,16 +330,21 @@ struct Stager {
     // Store into rows `rows`, `rows` + rp, ... (no ring wrap).
     // Store the fetched chunk as 16 gray levels at `p`, zero outside the
     // image.  Chunks outside are rare (edge tiles, rows beyond the image):
-    // they are overwritten with zeros behind the uniform zero_free test, which
-    // the empty volatile asm keeps a branch (as selects, the masking would
-    // run on every step).
+    // they are overwritten with zeros (or, the chunk that holds a row's last
+    // column, with its shifted levels) behind the uniform zero_free test,
+    // which the empty volatile asm keeps a branch (as selects, the masking
+    // would run on every step).
     template <class P>
     __device__ __forceinline__ void put(const PageArgs &a, P *p, int xr0, bool clamp) const {
         const uint4 v = chunk_gray<C, BODY != kEdge>(k, xr0 + 16 * job_q, a.W, clamp);
-        *p = u32x4{v.x, v.y, v.z, v.w};
+        const u32x4 g = u32x4{v.x, v.y, v.z, v.w};
+        *p = g;
         if (!zero_free) {
             asm volatile("");
-            if (!in_image) *p = u32x4{0u, 0u, 0u, 0u};
+            if (!in_image)
+                *p = u32x4{0u, 0u, 0u, 0u};
+            else if (WIDE && cut)
+                *p = shift_out(g, cut);
         }
     }
 
@@ -614,10 +638,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
     uint32_t *Vb2 = Va2 + RB * VAP;
     const int base = Y0 - lo - 1;  // image row held by ring slot 0
 
-    // Clamp loads and mask bytes in edge tiles: some of columns [xr0, xr0 +
-    // rp), or the one extra word a chunk may read past its last byte, lie
-    // outside the row (run_tile sends such tiles of unaligned pages to the
-    // kEdge body).
+    // Clamp loads and mask bytes in the kEdge body: some of columns [xr0,
+    // xr0 + rp), or the one extra word a chunk may read past its last byte,
+    // may lie outside the row.
     constexpr bool INT = BODY == kAligned;
     constexpr bool clamp = BODY == kEdge;
 
@@ -989,7 +1012,7 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
                     else
                         store_nt4(p, ow[0]);
                 }
-            } else if (BODY == kWide) {  // every output of an interior tile lies inside the row
+            } else if (BODY == kWide && xs + OPT <= a.W) {  // every output inside the row
                 glb_u8 *p = uniform_global(a.out + (size_t)y0 * (size_t)a.pitch_out) + out_off;
                 if (OPT == 8)
                     store_nt8_a1(p, ow[0], ow[OPT / 4 - 1]);
@@ -1021,10 +1044,9 @@ __device__ __forceinline__ void process_tile(const PageArgs &a, int tile, uint8_
 // launch): input rows 16-byte aligned and a multiple of 16 pixels wide, so
 // every 16-pixel chunk lies wholly inside or outside the image and staging
 // loads whole chunks with no per-byte masking; output rows 8-byte aligned, so
-// every thread stores its outputs with one store.  Other pages take, per tile
-// (a uniform choice), the wide body when every staged column lies inside the
-// row and both pitches are below 2^28 (unaligned 16-byte loads and 8-byte
-// stores), else the edge body.  All
+// every thread stores its outputs with one store.  Other pages take the wide
+// body when they are at least 16 pixels wide and both pitches are below 2^28
+// (unaligned 16-byte loads and 8-byte stores), else the edge body.  All
 // bodies produce identical bytes.  In each, tiles whose windows all span win
 // columns decide steps whose windows also span win rows with the per-tile
 // constants, and every other step with per-pixel n.  BLK selects the blocks
@@ -1036,9 +1058,7 @@ __device__ __forceinline__ void run_tile(const PageArgs &a, int tile, uint8_t *s
         process_tile<TW, C, RULE, STATS, kAligned, BLK>(a, tile, smem);
         return;
     }
-    const int X0 = (tile % a.tiles_x) * TW;
-    const int xr0 = floor16(X0 - a.lo - 1);  // as in process_tile
-    if (!a.small_pitch || xr0 < 0 || xr0 + a.rp + 4 > a.W)
+    if (!a.small_pitch || a.W < 16)
         process_tile<TW, C, RULE, STATS, kEdge, BLK>(a, tile, smem);
     else
         process_tile<TW, C, RULE, STATS, kWide, BLK>(a, tile, smem);
