@@ -118,7 +118,7 @@ __device__ __forceinline__ glb_u8 *uniform_global(uint8_t *p) {
     return (glb_u8 *)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Unaligned views (alignment 1) for the wide accesses of the interior tiles
+// Unaligned views (alignment 1) for the wide accesses of the tiles
 // of pages whose rows are not 16-byte aligned: gfx950 loads and stores them
 // whole (global memory runs in unaligned access mode under ROCm).
 typedef unsigned int u32x4_a1 __attribute__((ext_vector_type(4), aligned(1)));
@@ -525,7 +525,7 @@ __device__ __forceinline__ void store_nt4(glb_u8 *p, uint32_t w) {
     __builtin_nontemporal_store(w, (__attribute__((address_space(1))) uint32_t *)p);
 }
 
-// The same at any byte address (interior tiles of unaligned pages).
+// The same at any byte address (the wide body of unaligned pages).
 typedef uint32_t u32_a1 __attribute__((aligned(1)));
 __device__ __forceinline__ void store_nt8_a1(glb_u8 *p, uint32_t lo, uint32_t hi) {
     const u32x2_a1 v = {lo, hi};

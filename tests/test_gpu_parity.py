@@ -279,6 +279,31 @@ def test_interior_tiles_full_compare(bz, oracle_mod, C, rule, win, k):
     assert np.array_equal(out.cpu().numpy(), aligned)
 
 
+@pytest.mark.parametrize("C", [1, 3])
+def test_every_row_end_overhang(bz, oracle_mod, C):
+    """Widths 14..33: every position of the row's last column inside its
+    16-pixel chunk (the chunk that reaches past the row end loads the row's
+    last 16 pixels and shifts them; overhangs 1..15), the narrowest pages
+    (below 16 pixels) and whole chunks; compared with the oracle pixel by
+    pixel, and at a one-byte input and output offset byte for byte."""
+    import pagegen
+    H = 24
+    for W in range(14, 34):
+        img = pagegen.page(H, W, 1, seed=4000 + 10 * W + C, channels=C)
+        for win, rule, k in ((15, 0, 0.5), (61, 0, 0.34), (31, 1, -0.2)):
+            full_check(bz, oracle_mod, img, win, k, 128.0, rule, f"overhang {H}x{W}x{C} win {win}")
+            base = gpu_out(bz, img, win, f32(k), 128.0, rule)
+            ibuf = torch.zeros(img.size + 16, dtype=torch.uint8, device="cuda")
+            shifted = ibuf[1:1 + img.size].view(*img.shape)
+            shifted.copy_(torch.from_numpy(img))
+            obuf = torch.zeros(H * W + 16, dtype=torch.uint8, device="cuda")
+            out = obuf[1:1 + H * W].view(H, W)
+            bz.binarize(shifted, win, f32(k), 128.0, rule, out=out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), base), (W, C, win)
+            assert int(obuf[:1].sum()) == 0 and int(obuf[1 + H * W:].sum()) == 0
+
+
 @pytest.mark.parametrize("H,W,win", [(33, 16, 15), (40, 16, 101), (70, 48, 61), (129, 272, 31),
                                      (40, 272, 255), (60, 528, 101), (64, 1040, 15)])
 def test_aligned_pages_outside_chunks(bz, oracle_mod, H, W, win):
