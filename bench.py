@@ -367,6 +367,66 @@ def run_copy_stream(dev, mib: int = 1024, reps: int = 5) -> float:
     return gbps
 
 
+def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float = 10.0):
+    """Shader clock under the bench's own load: `step` (one pass of the five
+    cases) runs back to back, untimed, while a helper thread reads the GFX
+    clock of every XCD with `amd-smi metric --clock` (each reading takes a
+    tool start-up, longer than the whole timed region, so the readings are
+    taken over this run of the same steps right after it; the first comes
+    after 0.3 s of load).
+    None where the tool is missing or prints no GFX clocks."""
+    import re
+    import shutil
+    import subprocess
+    import threading
+    import torch
+    exe = shutil.which("amd-smi")
+    if not exe:
+        return None
+    readings, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            try:
+                r = subprocess.run([exe, "metric", "--clock"], capture_output=True, text=True, timeout=20)
+            except (OSError, subprocess.SubprocessError):
+                return
+            clk = [int(v) for v in re.findall(r"GFX_\d+:\s*\n\s*CLK:\s*(\d+)\s*MHz", r.stdout)]
+            if not clk:
+                return
+            readings.append(clk)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:  # under load before the first reading
+        for _ in range(20):
+            step()
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th.start()
+    while th.is_alive() and time.perf_counter() - t0 < limit_s and \
+            (len(readings) < min_samples or time.perf_counter() - t0 < seconds):
+        for _ in range(20):
+            step()
+        torch.cuda.synchronize()
+    stop.set()
+    for _ in range(20):  # keep the GPU busy until the reading in flight ends
+        if not th.is_alive():
+            break
+        for _ in range(20):
+            step()
+        torch.cuda.synchronize()
+    th.join(timeout=30)
+    if not readings:
+        return None
+    flat = sorted(v for clk in readings for v in clk)
+    return {"median": flat[len(flat) // 2], "p10": flat[len(flat) // 10], "p90": flat[(9 * len(flat)) // 10],
+            "min": flat[0], "max": flat[-1], "readings": len(readings),
+            "xcds": len(readings[0]), "max_clk": 2400,
+            "source": "amd-smi metric --clock (GFX clock of every XCD) during an untimed run of the "
+                      "same steps right after the timed region"}
+
+
 def compact_serve(res: dict) -> list:
     return [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
              if k in ("rate", "mode", "requests", "mean_batch", "p50_ms", "p99_ms", "gpix_s", "req_s")}
@@ -662,6 +722,7 @@ def main() -> int:
     rec["roofline"]["limited_by"] = ("valu-issue/latency" if valu and valu["frac"] > hbm_frac else "hbm")
     rec["roofline"]["frac_of_copy_stream"] = achieved / copy_stream_gbps
     if not args.no_extras:
+        rec["sclk_mhz"] = sample_sclk(lambda: [launch(c) for c in CASES])
         del ins, outs
         torch.cuda.empty_cache()
         extras = {}
