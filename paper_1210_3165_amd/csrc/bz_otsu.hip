@@ -11,9 +11,11 @@
 //                as the workgroup's row of 256 counts in the workspace (plain
 //                stores: no device atomics, no fences).
 //   otsu_select  one workgroup sums the rows into the histogram and selects
-//                k*: prefix counts and level sums by a block scan, the
-//                between-class variance w0 w1 (mu0 - mu1)^2 of every split in
-//                fp64, and the first split of largest variance.  It stores the
+//                k*: prefix counts and level sums by wave scans over four
+//                waves of 64 levels joined by one barrier, the between-class
+//                variance w0 w1 (mu0 - mu1)^2 of every split in fp64, and the
+//                first split of largest variance (wave reductions, then over
+//                the four waves).  It stores the
 //                histogram, k* and T = k* + 1 in the workspace.
 //   otsu_apply   out = 0 where f < T, 255 elsewhere (Eq. 2), 16 pixels per
 //                lane per step, again from 16-byte loads and stores (the
@@ -96,10 +98,12 @@ __global__ __launch_bounds__(kSelectThreads) void otsu_select(uint32_t *__restri
                                                               uint32_t *__restrict__ copy) {
     constexpr int kParts = kSelectThreads / 64;  // rows summed in parallel
     __shared__ uint4 part[kParts][64];
-    __shared__ uint32_t sn[256];
-    __shared__ uint64_t ss[256];
-    __shared__ double sv[256];
-    __shared__ int si[256];
+    __shared__ uint32_t wn[4];              // per wave of levels: total count
+    __shared__ unsigned long long ws64[4];  // and total level sum
+    __shared__ double sv[4];
+    __shared__ int si[4];
+    uint32_t n_lvl = 0;                     // this thread's level: prefix count
+    unsigned long long s_lvl = 0;           // and prefix level sum
     const int tid = threadIdx.x;
     {
         // thread: levels 4q..4q+3 (q = tid % 64) of rows tid / 64 + 16 i,
@@ -130,47 +134,72 @@ __global__ __launch_bounds__(kSelectThreads) void otsu_select(uint32_t *__restri
         part[tid >> 6][tid & 63] = acc;
     }
     __syncthreads();
+    // Levels 0..255 on the first four waves, level = tid: inclusive prefix
+    // sums of the counts and level sums inside each wave (shuffles), then
+    // the totals of the waves before it (one barrier); the first split of
+    // largest variance per wave, then over the four waves (one barrier).
     uint32_t h = 0;
     if (tid < 256) {
         const uint32_t *pw = reinterpret_cast<const uint32_t *>(&part[0][0]);
 #pragma unroll
         for (int p = 0; p < kParts; ++p) h += pw[p * 256 + tid];
-        sn[tid] = h;
-        ss[tid] = (uint64_t)tid * h;
-    }
-    __syncthreads();
-    // inclusive prefix sums of counts and level sums
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t a = 0;
-        uint64_t b = 0;
-        if (tid < 256 && tid >= off) {
-            a = sn[tid - off];
-            b = ss[tid - off];
-        }
-        __syncthreads();
-        if (tid < 256) {
-            sn[tid] += a;
-            ss[tid] += b;
-        }
-        __syncthreads();
-    }
-    if (tid < 256) {
-        sv[tid] = between_var(sn[tid], ss[tid], sn[255], ss[255]);
-        si[tid] = tid;
-    }
-    __syncthreads();
-    // first split of largest variance
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-            const double vo = sv[tid + off];
-            const int io = si[tid + off];
-            if (vo > sv[tid] || (vo == sv[tid] && io < si[tid])) {
-                sv[tid] = vo;
-                si[tid] = io;
+        const int lane = tid & 63;
+        uint32_t n0 = h;
+        unsigned long long s0 = (unsigned long long)tid * h;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t a = __shfl_up(n0, off, 64);
+            const unsigned long long b = __shfl_up(s0, off, 64);
+            if (lane >= off) {
+                n0 += a;
+                s0 += b;
             }
         }
-        __syncthreads();
+        if (lane == 63) {
+            wn[tid >> 6] = n0;
+            ws64[tid >> 6] = s0;
+        }
+        n_lvl = n0;
+        s_lvl = s0;
     }
+    __syncthreads();
+    if (tid < 256) {
+        const int w = tid >> 6, lane = tid & 63;
+        uint32_t n = 0;
+        unsigned long long s = 0;
+        for (int i = 0; i < 4; ++i) {
+            if (i < w) {
+                n_lvl += wn[i];
+                s_lvl += ws64[i];
+            }
+            n += wn[i];
+            s += ws64[i];
+        }
+        double v = between_var(n_lvl, s_lvl, n, s);
+        int k = tid;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double vo = __shfl_xor(v, off, 64);
+            const int ko = __shfl_xor(k, off, 64);
+            if (vo > v || (vo == v && ko < k)) {
+                v = vo;
+                k = ko;
+            }
+        }
+        if (lane == 0) {
+            sv[w] = v;
+            si[w] = k;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {  // waves in level order: a later wave wins only with a larger variance
+        for (int w = 1; w < 4; ++w)
+            if (sv[w] > sv[0]) {
+                sv[0] = sv[w];
+                si[0] = si[w];
+            }
+    }
+    __syncthreads();
     if (tid < 256) ws[kWsHist + tid] = h;
     if (tid == 0) {
         ws[kWsK] = (uint32_t)si[0];
