@@ -367,19 +367,22 @@ def run_copy_stream(dev, mib: int = 1024, reps: int = 5) -> float:
     return gbps
 
 
-def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float = 10.0):
+def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float = 10.0, sync=None):
     """Shader clock under the bench's own load: `step` (one pass of the five
     cases) runs back to back, untimed, while a helper thread reads the GFX
     clock of every XCD with `amd-smi metric --clock` (each reading takes a
     tool start-up, longer than the whole timed region, so the readings are
     taken over this run of the same steps right after it; the first comes
     after 0.3 s of load).
-    None where the tool is missing or prints no GFX clocks."""
+    None where the tool is missing or prints no GFX clocks.  `sync` waits
+    for the launched steps (torch.cuda.synchronize by default)."""
     import re
     import shutil
     import subprocess
     import threading
-    import torch
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
     exe = shutil.which("amd-smi")
     if not exe:
         return None
@@ -401,22 +404,21 @@ def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float
     while time.perf_counter() - t0 < 0.3:  # under load before the first reading
         for _ in range(20):
             step()
-        torch.cuda.synchronize()
+        sync()
     t0 = time.perf_counter()
     th.start()
     while th.is_alive() and time.perf_counter() - t0 < limit_s and \
             (len(readings) < min_samples or time.perf_counter() - t0 < seconds):
         for _ in range(20):
             step()
-        torch.cuda.synchronize()
+        sync()
     stop.set()
-    for _ in range(20):  # keep the GPU busy until the reading in flight ends
-        if not th.is_alive():
-            break
+    t_stop = time.perf_counter()
+    while th.is_alive() and time.perf_counter() - t_stop < 25:  # busy until the reading in flight ends
         for _ in range(20):
             step()
-        torch.cuda.synchronize()
-    th.join(timeout=30)
+        sync()
+    th.join(timeout=5)
     if not readings:
         return None
     flat = sorted(v for clk in readings for v in clk)

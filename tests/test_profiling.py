@@ -2,6 +2,7 @@
 records, and the bench's use of those records (no GPU involved)."""
 import csv
 import json
+import os
 
 import pytest
 
@@ -98,3 +99,35 @@ def test_percentile_matches_numpy():
         v = list(rng.uniform(1, 100, n))
         for q in (10, 50, 90):
             assert abs(profiling._pct(v, q) - float(np.percentile(v, q))) < 1e-9
+
+
+def _fake_amd_smi(tmp_path, text):
+    tool = tmp_path / "amd-smi"
+    (tmp_path / "out.txt").write_text(text)
+    tool.write_text(f"#!/bin/sh\ncat {tmp_path / 'out.txt'}\n")
+    tool.chmod(0o755)
+    return str(tmp_path)
+
+
+def test_sclk_sampler_reads_every_xcd_under_load(tmp_path, monkeypatch):
+    """The bench's clock sampler parses the GFX clock of each XCD from the
+    tool's text, keeps the steps running while it reads, and summarises the
+    readings; the memory clock and limits are not taken for GFX clocks."""
+    text = ("GPU: 0\n    CLOCK:\n"
+            + "".join(f"        GFX_{i}:\n            CLK: {2390 + i} MHz\n            MIN_CLK: 500 MHz\n"
+                      f"            MAX_CLK: 2400 MHz\n" for i in range(8))
+            + "        MEM_0:\n            CLK: 2000 MHz\n")
+    monkeypatch.setenv("PATH", _fake_amd_smi(tmp_path, text) + os.pathsep + os.environ["PATH"])
+    steps = []
+    res = bench.sample_sclk(lambda: steps.append(1), min_samples=2, seconds=0.1, limit_s=5.0,
+                            sync=lambda: None)
+    assert res is not None and res["xcds"] == 8 and res["readings"] >= 2
+    assert (res["min"], res["max"]) == (2390, 2397) and 2390 <= res["median"] <= 2397
+    assert len(steps) > 0
+
+
+def test_sclk_sampler_without_clock_readings(tmp_path, monkeypatch):
+    monkeypatch.setenv("PATH", _fake_amd_smi(tmp_path, "no GPU found\n") + os.pathsep + os.environ["PATH"])
+    assert bench.sample_sclk(lambda: None, seconds=0.05, limit_s=1.0, sync=lambda: None) is None
+    monkeypatch.setenv("PATH", str(tmp_path / "empty"))
+    assert bench.sample_sclk(lambda: None, seconds=0.05, limit_s=1.0, sync=lambda: None) is None
