@@ -423,7 +423,8 @@ def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float
         return None
     flat = sorted(v for clk in readings for v in clk)
     return {"median": flat[len(flat) // 2], "p10": flat[len(flat) // 10], "p90": flat[(9 * len(flat)) // 10],
-            "min": flat[0], "max": flat[-1], "readings": len(readings),
+            "min": flat[0], "max": flat[-1], "share_below_2000": sum(v < 2000 for v in flat) / len(flat),
+            "readings": len(readings),
             "xcds": len(readings[0]), "max_clk": 2400,
             "source": "amd-smi metric --clock (GFX clock of every XCD) during an untimed run of the "
                       "same steps right after the timed region"}
