@@ -7,14 +7,18 @@ buffer pair from a rotating pool larger than the 256 MB Infinity Cache, so the
 bytes come from HBM.  Inputs are resident in HBM before timing starts.
 
 Prints ONE JSON line (rank 0):
-  value      Gpixel/s over the timed steps (pixels binarized / time)
+  value      Gpixel/s over the timed steps (pixels binarized / time), the
+             launches of each window taken in turn by --streams streams (the
+             pages are independent, so one launch's last tiles overlap the
+             next one's first)
+  value_one_stream  the same K steps with every launch on one stream
   roofline   achieved algorithmic HBM GB/s of the dominant kernel (Sauvola,
              gray, 256-column tiles: 2 bytes per pixel) from HIP events
-             around each window's run of back-to-back launches, against the
-             8 TB/s MI355X peak
+             around each window's run of back-to-back launches on one stream
+             (the kernel's own duration), against the 8 TB/s MI355X peak
   cpu_baseline  the CPU oracle timed on this host on a bounded pixel sample
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--streams S] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -368,12 +372,12 @@ def run_copy_stream(dev, mib: int = 1024, reps: int = 5) -> float:
 
 
 def sample_sclk(step, min_samples: int = 2, seconds: float = 2.0, limit_s: float = 10.0, sync=None):
-    """Shader clock under the bench's own load: `step` (one pass of the five
-    cases) runs back to back, untimed, while a helper thread reads the GFX
-    clock of every XCD with `amd-smi metric --clock` (each reading takes a
-    tool start-up, longer than the whole timed region, so the readings are
-    taken over this run of the same steps right after it; the first comes
-    after 0.3 s of load).
+    """Shader clock under the bench's own load: `step` (steps of the five
+    cases, launched as for `value`) runs back to back, untimed, while a
+    helper thread reads the GFX clock of every XCD with `amd-smi metric
+    --clock` (each reading takes a tool start-up, longer than the whole timed
+    region, so the readings are taken over this run of the same steps right
+    after it; the first comes after 0.3 s of load).
     None where the tool is missing or prints no GFX clocks.  `sync` waits
     for the launched steps (torch.cuda.synchronize by default)."""
     import re
@@ -562,6 +566,9 @@ def main() -> int:
                     help="page4096: skip the batch, serve, latency and copy figures added to the line")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--streams", type=int, default=3,
+                    help="page4096: streams the timed launches take in turn for `value` (the launch "
+                         "stream and S - 1 more; 1: one stream)")
     ap.add_argument("--lds-cap", type=int, default=0,
                     help="batch: LDS bytes per workgroup (0: default, -1: autotune cap and tile height)")
     ap.add_argument("--batch-tile-h", type=int, default=0, help="batch: tile height (0: default)")
@@ -633,36 +640,76 @@ def main() -> int:
         idx += 1
         bz.binarize(ins[b], win, k, 128.0, rule, out=outs[b])
 
+    # the launch stream and S - 1 more, all at the default priority
+    streams = [stream] + [torch.cuda.Stream(dev) for _ in range(max(0, args.streams - 1))]
+
+    def run_overlapped(k_steps):
+        """k_steps steps grouped by case, launch j of a case on streams[j % S]:
+        the other streams start after an event on the launch stream, which
+        waits for their last launches before the case's end event."""
+        evs = []
+        for c in CASES:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for st in streams[1:]:
+                st.wait_event(e0)
+            for j in range(k_steps):
+                st = streams[j % len(streams)]
+                if st is stream:
+                    launch(c)
+                else:
+                    with torch.cuda.stream(st):
+                        launch(c)
+            for st in streams[1:]:
+                e = torch.cuda.Event()
+                e.record(st)
+                stream.wait_event(e)
+            e1.record(stream)
+            evs.append((e0, e1))
+        return evs
+
     for _ in range(args.warmup):
         for c in CASES:
             launch(c)
+    run_overlapped(args.warmup)
     torch.cuda.synchronize()
 
-    # timed region: K steps, grouped by case.  The K launches of one case run
-    # back to back (each on the next buffer pair of the pool), bracketed by
-    # one pair of HIP events on the launch stream: no event marker sits
-    # between two launches of the timed work.  The five cases follow each
-    # other on the same stream, so the first start and the last end bracket
-    # all K steps.
+    # kernel durations (the roofline and value_one_stream): K steps, grouped
+    # by case.  The K launches of one case run back to back on the launch
+    # stream (each on the next buffer pair of the pool), bracketed by one
+    # pair of HIP events: no event marker sits between two launches.  The
+    # five cases follow each other on the same stream, so the first start and
+    # the last end bracket all K steps.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in CASES]
     torch.cuda.synchronize()
-    t_wall = time.perf_counter()
     for i, c in enumerate(CASES):
         ev[i][0].record(stream)
         for _ in range(args.steps):
             launch(c)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    total_ms_one = ev[0][0].elapsed_time(ev[-1][1])
     case_ms = [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
+
+    # timed region of `value`: the same K steps, grouped by case, with the
+    # launches of each case taken in turn by the streams; the first case's
+    # start event and the last case's end event, both on the launch stream,
+    # bracket all K steps
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    evo = run_overlapped(args.steps)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = evo[0][0].elapsed_time(evo[-1][1])
+    case_ms_overlapped = [e0.elapsed_time(e1) / args.steps for e0, e1 in evo]
 
     cases = []
     for i, (rule, win, k) in enumerate(CASES):
         ms = case_ms[i]
         cases.append({"rule": RULE_NAME[rule], "win": win, "k": k, "ms": ms,
                       "gpix_s": px / (ms * 1e-3) / 1e9,
-                      "hbm_frac": 2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS})
+                      "hbm_frac": 2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                      "gpix_s_streams": px / (case_ms_overlapped[i] * 1e-3) / 1e9})
     # dominant kernel: the Sauvola gray launches (4 of the 5 per step)
     avg_ms = float(np.mean([case_ms[i] for i, c in enumerate(CASES) if c[0] == 0]))
     achieved = 2 * px / (avg_ms * 1e-3) / 1e9
@@ -684,6 +731,7 @@ def main() -> int:
     rec = {
         "metric": METRIC,
         "value": px * len(CASES) / (step_ms * 1e-3) / 1e9,
+        "value_one_stream": px * len(CASES) / (total_ms_one / args.steps * 1e-3) / 1e9,
         "unit": "Gpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -700,6 +748,7 @@ def main() -> int:
             "H": S, "W": S, "channels": 1,
             "tiles": {str(w): list(bz.default_tile(S, S, 1, w)) for _, w, _ in CASES},
             "pool_pairs": n_pairs,
+            "streams": len(streams),
         },
         "roofline": {
             "bound": "hbm",
@@ -725,7 +774,7 @@ def main() -> int:
     rec["roofline"]["limited_by"] = ("valu-issue/latency" if valu and valu["frac"] > hbm_frac else "hbm")
     rec["roofline"]["frac_of_copy_stream"] = achieved / copy_stream_gbps
     if not args.no_extras:
-        rec["sclk_mhz"] = sample_sclk(lambda: [launch(c) for c in CASES])
+        rec["sclk_mhz"] = sample_sclk(lambda: run_overlapped(4))  # the load of `value`
         del ins, outs
         torch.cuda.empty_cache()
         extras = {}
