@@ -87,6 +87,41 @@ def test_side_stream_entry_points_and_reserved_buffers(bz, monkeypatch):
         assert bool((j == 7).all())
 
 
+def test_concurrent_pages_on_three_streams(bz):
+    """The bench's overlapped launches: each of the five 4096^2 cases
+    launched six times, the launches taken in turn by the current stream and
+    two more (the others waiting on an event of the current one, which waits
+    for their last launches), every launch into its own output; each output
+    equals the same case run alone on one stream, byte for byte."""
+    page = torch.from_numpy(pagegen.config1()[0].img).cuda()
+    cases = [(0, 15, 0.5), (0, 31, 0.5), (0, 61, 0.5), (0, 101, 0.5), (1, 31, -0.2)]
+    cases = [(r, w, float(np.float32(k))) for r, w, k in cases]
+    ref = {}
+    for r, w, k in cases:
+        ref[(r, w)] = bz.binarize(page, w, k, 128.0, r)
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    streams = [main, torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = {}
+    for r, w, k in cases:
+        e0 = torch.cuda.Event()
+        e0.record(main)
+        for st in streams[1:]:
+            st.wait_event(e0)
+        for j in range(6):
+            o = torch.empty_like(page)
+            with torch.cuda.stream(streams[j % 3]):
+                bz.binarize(page, w, k, 128.0, r, out=o)
+            outs[(r, w, j)] = o
+        for st in streams[1:]:
+            e = torch.cuda.Event()
+            e.record(st)
+            main.wait_event(e)
+    torch.cuda.synchronize()
+    for (r, w, j), o in outs.items():
+        assert torch.equal(o, ref[(r, w)]), (r, w, j)
+
+
 def test_otsu_reads_follow_a_side_stream_run(bz, oracle_mod):
     a = pagegen.page(512, 384, 600, seed=83)
     b = np.ascontiguousarray(255 - a // 2)
