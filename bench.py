@@ -40,6 +40,14 @@ CASES = [  # (rule, win, k) of the 4096^2 workload
     (0, 15, 0.5), (0, 31, 0.5), (0, 61, 0.5), (0, 101, 0.5), (1, 31, -0.2),
 ]
 RULE_NAME = {0: "sauvola", 1: "niblack"}
+# Tiles of the three-stream pass, by window.  The library's default sizes a
+# launch to fill the GPU alone in one round of 64-row tiles; with launches
+# overlapping on several streams that balance matters less and taller tiles
+# spend fewer rows on each tile's window start-up.  At win 101 a 128-row tile
+# count no longer exceeds what the ring layout runs at once, so the page
+# falls back to the ring at two workgroups per CU: 96 rows keep the blocks
+# layout there.  Every tile shape gives the same bytes.
+STREAM_TILES = {15: (256, 128), 31: (256, 128), 61: (256, 128), 101: (256, 96)}
 DOMINANT = "bz_page_kernel<256, gray, sauvola>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bz_page_kernel_sauvola_gray_4096.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_bz_page_kernel_sauvola_gray_4096.json")
@@ -633,12 +641,12 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     idx = 0
 
-    def launch(case):
+    def launch(case, tile=None):
         nonlocal idx
         rule, win, k = case
         b = idx % n_pairs
         idx += 1
-        bz.binarize(ins[b], win, k, 128.0, rule, out=outs[b])
+        bz.binarize(ins[b], win, k, 128.0, rule, out=outs[b], tile=tile)
 
     # the launch stream and S - 1 more, all at the default priority
     streams = [stream] + [torch.cuda.Stream(dev) for _ in range(max(0, args.streams - 1))]
@@ -646,9 +654,11 @@ def main() -> int:
     def run_overlapped(k_steps):
         """k_steps steps grouped by case, launch j of a case on streams[j % S]:
         the other streams start after an event on the launch stream, which
-        waits for their last launches before the case's end event."""
+        waits for their last launches before the case's end event.  Tiles:
+        STREAM_TILES on more than one stream, else the library's default."""
         evs = []
         for c in CASES:
+            tile = STREAM_TILES[c[1]] if len(streams) > 1 else None
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for st in streams[1:]:
@@ -656,10 +666,10 @@ def main() -> int:
             for j in range(k_steps):
                 st = streams[j % len(streams)]
                 if st is stream:
-                    launch(c)
+                    launch(c, tile)
                 else:
                     with torch.cuda.stream(st):
-                        launch(c)
+                        launch(c, tile)
             for st in streams[1:]:
                 e = torch.cuda.Event()
                 e.record(st)
@@ -749,6 +759,8 @@ def main() -> int:
             "tiles": {str(w): list(bz.default_tile(S, S, 1, w)) for _, w, _ in CASES},
             "pool_pairs": n_pairs,
             "streams": len(streams),
+            "tiles_streams": ({str(w): list(STREAM_TILES[w]) for _, w, _ in CASES} if len(streams) > 1
+                              else None),
         },
         "roofline": {
             "bound": "hbm",

@@ -91,8 +91,10 @@ def test_concurrent_pages_on_three_streams(bz):
     """The bench's overlapped launches: each of the five 4096^2 cases
     launched six times, the launches taken in turn by the current stream and
     two more (the others waiting on an event of the current one, which waits
-    for their last launches), every launch into its own output; each output
-    equals the same case run alone on one stream, byte for byte."""
+    for their last launches), every launch into its own output, alternately
+    with the default tiles and the taller tiles of the bench's three-stream
+    pass; each output equals the same case run alone on one stream, byte for
+    byte."""
     page = torch.from_numpy(pagegen.config1()[0].img).cuda()
     cases = [(0, 15, 0.5), (0, 31, 0.5), (0, 61, 0.5), (0, 101, 0.5), (1, 31, -0.2)]
     cases = [(r, w, float(np.float32(k))) for r, w, k in cases]
@@ -110,8 +112,9 @@ def test_concurrent_pages_on_three_streams(bz):
             st.wait_event(e0)
         for j in range(6):
             o = torch.empty_like(page)
+            tile = None if j % 2 == 0 else ((256, 96) if w == 101 else (256, 128))
             with torch.cuda.stream(streams[j % 3]):
-                bz.binarize(page, w, k, 128.0, r, out=o)
+                bz.binarize(page, w, k, 128.0, r, out=o, tile=tile)
             outs[(r, w, j)] = o
         for st in streams[1:]:
             e = torch.cuda.Event()
