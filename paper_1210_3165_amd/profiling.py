@@ -96,6 +96,43 @@ def trace_summary(d: str, prefix: str, title: str, command: str, note: str = "",
     return "\n".join(out) + "\n"
 
 
+def overlap_summary(d: str, prefix: str, kernel: str, min_launches: int = 1) -> str:
+    """Runs of consecutive dispatches of one kernel and launch shape, in start
+    order: per run the launches, their mean duration, the run's span (first
+    start to last end), the summed durations over the span (the mean number
+    of launches in flight) and the share of the span with two or more in
+    flight, for runs of at least min_launches.  A markdown table."""
+    rows = [r for r in _rows(f"{d}/{prefix}_kernel_trace.csv") if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    runs = []
+    for r in rows:
+        key = (_short(r["Kernel_Name"]).split("(")[0], int(r["Grid_Size_X"]))
+        iv = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+        if runs and runs[-1][0] == key:
+            runs[-1][1].append(iv)
+        else:
+            runs.append((key, [iv]))
+    out = ["| run | kernel | grid threads | launches | mean us | span us | span / launch us "
+           "| in flight (mean) | span with 2+ in flight |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for i, ((name, grid), ivs) in enumerate(runs):
+        if len(ivs) < min_launches:
+            continue
+        t0, t1 = min(a for a, _ in ivs), max(b for _, b in ivs)
+        busy = sum(b - a for a, b in ivs)
+        ev = sorted([(a, 1) for a, _ in ivs] + [(b, -1) for _, b in ivs])
+        depth, last, multi = 0, t0, 0
+        for t, dlt in ev:
+            if depth >= 2:
+                multi += t - last
+            depth += dlt
+            last = t
+        span = max(t1 - t0, 1)
+        out.append(f"| {i} | `{name}` | {grid} | {len(ivs)} | {busy / len(ivs) / 1e3:.1f} | {span / 1e3:.1f} | "
+                   f"{span / len(ivs) / 1e3:.1f} | {busy / span:.2f} | {multi / span:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def _counter(path, counter):
     per = defaultdict(list)
     for r in _rows(path):
@@ -206,6 +243,11 @@ def main(argv=None) -> int:
     f.add_argument("--workload", required=True)
     f.add_argument("--command", action="append", default=[])
     f.add_argument("--sources", default="binarize.hip,bz_common.hpp,bz_tile.hpp")
+    o = sub.add_parser("overlap")
+    o.add_argument("dir")
+    o.add_argument("prefix")
+    o.add_argument("--kernel", required=True, help="substring of the kernel name")
+    o.add_argument("--min-launches", type=int, default=1)
     v = sub.add_parser("valu")
     v.add_argument("sq_csv", nargs="+")
     v.add_argument("--kernel", required=True, help="substring of the kernel name")
@@ -216,6 +258,8 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         sys.stdout.write(trace_summary(a.dir, a.prefix, a.title, a.command, a.note))
+    elif a.cmd == "overlap":
+        sys.stdout.write(overlap_summary(a.dir, a.prefix, a.kernel, a.min_launches))
     elif a.cmd == "valu":
         rec = valu(a.sq_csv, a.kernel, a.pixels, a.workload, a.command, tuple(a.sources.split(",")))
         sys.stdout.write(json.dumps(rec, indent=1) + "\n")

@@ -131,3 +131,24 @@ def test_sclk_sampler_without_clock_readings(tmp_path, monkeypatch):
     assert bench.sample_sclk(lambda: None, seconds=0.05, limit_s=1.0, sync=lambda: None) is None
     monkeypatch.setenv("PATH", str(tmp_path / "empty"))
     assert bench.sample_sclk(lambda: None, seconds=0.05, limit_s=1.0, sync=lambda: None) is None
+
+
+def test_overlap_summary_counts_launches_in_flight(tmp_path):
+    """Runs split where the kernel or grid changes; a serial run has one
+    launch in flight, an overlapping one reports its mean depth and the share
+    of its span with two or more in flight."""
+    cols = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"]
+    rows = [("void k<1>(A)", 100, 0, 10_000), ("void k<1>(A)", 100, 10_000, 20_000),   # serial
+            ("void k<1>(A)", 50, 30_000, 40_000), ("void k<1>(A)", 50, 35_000, 45_000),  # overlap
+            ("void other(B)", 100, 50_000, 60_000)]
+    with open(tmp_path / "t_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(cols)
+        w.writerows(rows)
+    table = profiling.overlap_summary(str(tmp_path), "t", "k<1>").strip().split("\n")
+    assert len(table) == 4
+    serial = [c.strip() for c in table[2].split("|")[1:-1]]
+    over = [c.strip() for c in table[3].split("|")[1:-1]]
+    assert serial[2:] == ["100", "2", "10.0", "20.0", "10.0", "1.00", "0.00"]
+    assert over[2:] == ["50", "2", "10.0", "15.0", "7.5", "1.33", "0.33"]
+    assert len(profiling.overlap_summary(str(tmp_path), "t", "k<1>", min_launches=3).strip().split("\n")) == 2
