@@ -12,6 +12,8 @@ Prints ONE JSON line (rank 0):
              pages are independent, so one launch's last tiles overlap the
              next one's first)
   value_one_stream  the same K steps with every launch on one stream
+  hbm_frac   the timed steps' algorithmic bytes (2 per pixel) per second
+             against the 8 TB/s MI355X peak
   roofline   achieved algorithmic HBM GB/s of the dominant kernel (Sauvola,
              gray, 256-column tiles: 2 bytes per pixel) from HIP events
              around each window's run of back-to-back launches on one stream
@@ -742,6 +744,10 @@ def main() -> int:
         "metric": METRIC,
         "value": px * len(CASES) / (step_ms * 1e-3) / 1e9,
         "value_one_stream": px * len(CASES) / (total_ms_one / args.steps * 1e-3) / 1e9,
+        # the whole timed job's algorithmic bytes (2 per pixel) over its time,
+        # as a share of the HBM peak; roofline.frac is the same for one kernel
+        # from its own launch duration
+        "hbm_frac": 2 * px * len(CASES) / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "unit": "Gpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
