@@ -32,6 +32,7 @@ from . import Batch, binarize, binarize_staged, tile_lds
 WIN_BUCKETS = (15, 31, 61, 101, 151, 201, 255)
 SINGLE_TILES = ((256, 32), (256, 64), (256, 128), (256, 256), (128, 64), (128, 128), (128, 256))
 BATCH_TILE_H = (128, 256, 512)
+BATCH_SAMPLE = 512  # pages the batch tuner times
 LDS_4_PER_CU = 160 * 1024 // 4 - 64   # cap that lets 4 workgroups share a CU
 LDS_2_PER_CU = 160 * 1024 // 2 - 64
 
@@ -178,9 +179,12 @@ class Tuner:
             hit = self.cache.get(key)
         if hit:
             return dict(hit["config"])
-        # time on a subsample of the shapes (at most 48 pages)
-        step = max(1, len(specs) // 48)
-        sample = specs[::step][:48]
+        # time on the shapes themselves, up to 512 pages (an evenly spaced
+        # subsample of larger sets): a batch run of that many pages takes
+        # milliseconds, and smaller subsamples of uneven sets misjudged the
+        # tile height
+        step = max(1, -(-len(specs) // BATCH_SAMPLE))
+        sample = specs[::step][:BATCH_SAMPLE]
         pages = [(self._page(h, w, c), torch.empty((h, w), dtype=torch.uint8, device=self.device), win)
                  for h, w, c, win in sample]
         caps = [LDS_2_PER_CU]
