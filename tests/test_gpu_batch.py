@@ -71,6 +71,28 @@ def test_batch_equals_single_pages(bz, oracle_mod, use_graph):
             assert compare_out(out, ref.out, ref.gray, ref.t)["ok"]
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_narrow_pages_of_every_row_end_overhang(bz, oracle_mod, use_graph):
+    """One batch of narrow pages, widths 1..40 (below 16 pixels the edge row
+    body, above it the wide body with every overhang 1..15 of a row's last
+    chunk), gray and RGB, both rules: each equals the page run alone and the
+    oracle."""
+    import pagegen
+    from oracle.compare import compare_out
+    jobs = []
+    for W in range(1, 41):
+        C = 1 if W % 2 else 3
+        win, rule, k = ((15, 0, f32(0.5)), (31, 1, f32(-0.2)), (61, 0, f32(0.34)))[W % 3]
+        img = pagegen.page(20 + W % 7, W, 1, seed=5000 + W, channels=C)
+        jobs.append((img, win, k, 128.0, rule))
+    with bz.Batch(64) as B:
+        outs = run_batch(bz, B, jobs, use_graph)
+    for (img, win, k, R, rule), out in zip(jobs, outs):
+        assert np.array_equal(out, single(bz, img, win, k, R, rule)), (img.shape, win, rule)
+        ref = oracle_mod.binarize(img, win, k, R, rule)
+        assert compare_out(out, ref.out, ref.gray, ref.t)["ok"], (img.shape, win, rule)
+
+
 def test_graph_replays_with_changing_batches(bz):
     """One batch object, graph mode: batches with different page counts and
     kinds (forcing re-capture), each replayed several times with eager work
